@@ -1,0 +1,123 @@
+"""CPU oracle for the wavefront cell recurrence -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package.  The product library never imports, links or calls it, and it shares
+no code with the GPU path (the only shared module is the seeded input generator, which holds
+none of the method's arithmetic).
+
+The arithmetic lives in ``wf_oracle.c`` (plain row-by-row C, -O2, no fast-math, no FP
+contraction); this module only marshals numpy arrays.  See that file's header for the
+recurrence (reading R0: the paper does not state the cell recurrence; the reading, its
+boundary convention and its tie rule are listed in the design notes).
+
+    forward(C, precision)  -> (D, sel)      precision in {"f64", "f32", "i64"}
+    backward(sel, gD, gscore, precision) -> gC
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SEL_NONE, SEL_NW, SEL_N, SEL_W = 0, 1, 2, 3
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    i64, p = ctypes.c_int64, ctypes.c_void_p
+    for name in ("wfo_forward_f64", "wfo_forward_f32", "wfo_forward_i64"):
+        f = getattr(lib, name)
+        f.argtypes = [i64, i64, p, i64, p, i64, p]
+        f.restype = None
+    lib.wfo_backward_f64.argtypes = [i64, i64, p, p, i64, ctypes.c_double, p, i64]
+    lib.wfo_backward_f64.restype = None
+    lib.wfo_backward_f32.argtypes = [i64, i64, p, p, i64, ctypes.c_float, p, i64]
+    lib.wfo_backward_f32.restype = None
+    lib.wfo_version.restype = ctypes.c_int
+    if lib.wfo_version() != 1:
+        raise RuntimeError("stale oracle build")
+    _lib = lib
+    return lib
+
+
+_FWD = {"f64": ("wfo_forward_f64", np.float64),
+        "f32": ("wfo_forward_f32", np.float32),
+        "i64": ("wfo_forward_i64", np.int64)}
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def forward(C, precision: str = "f64", want_sel: bool = True):
+    """Row-by-row forward sweep.  Returns (D, sel); sel is None when want_sel is False.
+
+    C is converted to the precision's type first (float32 data widens exactly to float64;
+    integer data must fit int64)."""
+    lib = _load()
+    name, dt = _FWD[precision]
+    C = np.ascontiguousarray(np.asarray(C), dtype=dt)
+    if C.ndim != 2:
+        raise ValueError("C must be 2-D")
+    m, n = C.shape
+    D = np.empty((m, n), dtype=dt)
+    sel = np.empty((m, n), dtype=np.uint8) if want_sel else None
+    if m and n:
+        getattr(lib, name)(m, n, _ptr(C), n, _ptr(D), n, _ptr(sel) if want_sel else None)
+    return D, sel
+
+
+def score(C, precision: str = "f64"):
+    D, _ = forward(C, precision, want_sel=False)
+    return D[-1, -1]
+
+
+def backward(sel, gD=None, gscore=0.0, precision: str = "f64"):
+    """Routed adjoint for a fixed selection map; returns gC with the precision's type."""
+    lib = _load()
+    sel = np.ascontiguousarray(sel, dtype=np.uint8)
+    m, n = sel.shape
+    if precision == "f64":
+        dt, fn = np.float64, lib.wfo_backward_f64
+    elif precision == "f32":
+        dt, fn = np.float32, lib.wfo_backward_f32
+    else:
+        raise ValueError(precision)
+    gC = np.empty((m, n), dtype=dt)
+    g = None
+    if gD is not None:
+        g = np.ascontiguousarray(gD, dtype=dt)
+        assert g.shape == (m, n)
+    if m and n:
+        fn(m, n, _ptr(sel), _ptr(g) if g is not None else None, n, dt(gscore), _ptr(gC), n)
+    return gC
+
+
+def grad(C, gD=None, gscore=1.0, precision: str = "f64"):
+    """Convenience: forward for SEL, then the adjoint."""
+    D, sel = forward(C, precision if precision != "i64" else "f64")
+    return backward(sel, gD, gscore, precision), D
