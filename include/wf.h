@@ -1,0 +1,103 @@
+/*
+ * wf.h -- C ABI of libwf, the MI355X (gfx950) anti-diagonal wavefront sweep.
+ *
+ * The operation.  The paper this library accompanies (an arXiv study of sub-system sizes
+ * for the GPU tridiagonal partition method) does not state a cell recurrence; its only
+ * trace of one is a pair of unused preamble macros (2n-1 anti-diagonals of an n x n grid
+ * and a 3 n^2 per-sweep byte count).  The library implements the documented reading "R0"
+ * of a west / north / north-west cell recurrence:
+ *
+ *     D[i][j] = C[i][j] + min( D[i-1][j-1], D[i-1][j], D[i][j-1] ),   0 <= i < m, 0 <= j < n
+ *
+ * with the virtual boundary D[-1][-1] = 0 and D[-1][j] = D[i][-1] = +inf otherwise (row 0
+ * and column 0 are prefix sums).  score = D[m-1][n-1].  Predecessor selection, used by the
+ * adjoint, breaks ties in the order NW, N, W.  All m+n-1 anti-diagonals are swept on the
+ * device by one persistent kernel; no launch per diagonal.
+ *
+ * Conventions shared by every entry point:
+ *   - Sizes and leading dimensions are in ELEMENTS.  Matrices are row-major.
+ *   - Data pointers (C, D, score, ckpt, g_*) are DEVICE pointers owned by the caller; the
+ *     library never frees or retains them past the call's stream work.
+ *   - 'stream' is a hipStream_t passed as void* (NULL = the legacy default stream).  Every
+ *     entry point only enqueues work on 'stream' and returns; there is no host sync on the
+ *     hot path.  Results are bitwise reproducible run to run.
+ *   - Return value: WF_OK or an error code.  Arguments are validated before any device work;
+ *     on an argument error nothing is enqueued.  A device-side failure (a bounded wait that
+ *     expired) is reported by wf_last_async_error().
+ *   - The library keeps one internal workspace per device (handoff words, counters), created
+ *     on the first call on that device and grown when a larger shape arrives (growing
+ *     allocates and synchronizes the device).  Calls that share a device must be ordered
+ *     (one stream, or streams joined by events): two overlapping calls on one device race on
+ *     that workspace.
+ *   - Element types: WF_F32 (float, one IEEE add per cell, min exact), WF_F64 (double),
+ *     WF_I32 (int32; the caller guarantees (m+n-1) * max|C| < 2^31 - 1 so no sum overflows).
+ *     Inputs must be free of NaN and -inf; +inf marks a blocked cell.
+ */
+#ifndef WF_H
+#define WF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { WF_F32 = 0, WF_F64 = 1, WF_I32 = 2 } wf_dtype;
+
+enum {
+  WF_OK = 0,
+  WF_E_ARG = 1,         /* invalid argument (size, pointer, leading dimension, dtype)   */
+  WF_E_UNSUPPORTED = 2, /* valid but not supported by this build (e.g. a tile width)    */
+  WF_E_NOMEM = 3,       /* device allocation of the internal workspace failed           */
+  WF_E_DEVICE = 4,      /* a HIP runtime call failed                                    */
+  WF_E_TIMEOUT = 5      /* a bounded device-side wait expired (reported asynchronously) */
+};
+
+/*
+ * Forward sweep of one m x n instance.
+ *   C      [in]  m x n, leading dimension ldc >= n.
+ *   D      [out] m x n table, leading dimension ldd >= n; NULL = score-only mode (the table
+ *                is never written to memory; the sweep still runs over every cell).
+ *   score  [out] one element, D[m-1][n-1].  Required.
+ *   ckpt   [out] checkpoint grid for wf_backward, wf_ckpt_elems(m, n, ckpt_k) elements, or
+ *                NULL when ckpt_k == 0.  Layout: first the band rows -- D[64b+63][0..n-1] for
+ *                b = 0 .. ceil(m/64)-2, row after row -- then the block columns --
+ *                D[0..m-1][K q - 1] for q = 1 .. ceil(n/K)-1, column after column
+ *                (K = ckpt_k).  Rows are every 64 because the device sweep works on bands of
+ *                64 rows; K sets the column spacing.
+ *   ckpt_k      column spacing K of the checkpoint grid, 0 = no checkpoints, else 1..4096.
+ * Element type of every buffer is 'dtype'.
+ */
+int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void* D,
+               int64_t ldd, void* score, void* ckpt, int32_t ckpt_k, void* stream);
+
+/* Number of elements of the checkpoint grid written by wf_forward (0 when ckpt_k == 0, or
+ * -1 on invalid sizes). */
+int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k);
+
+/*
+ * Force the tile width (columns per handoff unit, 64 rows per band) used by later calls on
+ * this process: 16, 32 or 64, or 0 to return to the automatic choice.  Returns WF_E_ARG for
+ * any other value.  Used by the autotuner and the tests.
+ */
+int wf_set_tile(int32_t tile);
+
+/*
+ * Synchronizes 'stream', then reports and clears the device-side error state of the
+ * current device's workspace: WF_OK, or WF_E_TIMEOUT if a bounded wait expired in any call
+ * since the last check (the outputs of such a call are undefined).
+ */
+int wf_last_async_error(void* stream);
+
+/* Static, human-readable name of an error code. */
+const char* wf_error_string(int code);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int wf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WF_H */

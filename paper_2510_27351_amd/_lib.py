@@ -1,0 +1,62 @@
+"""ctypes binding of libwf.so (include/wf.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwf.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "wf.h")
+
+WF_F32, WF_F64, WF_I32 = 0, 1, 2
+WF_OK, WF_E_ARG, WF_E_UNSUPPORTED, WF_E_NOMEM, WF_E_DEVICE, WF_E_TIMEOUT = range(6)
+
+_lib = None
+
+
+class WfError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {error_string(code)} (code {code})")
+
+
+def load():
+    """Loads libwf.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libwf.so is not built ({LIB_PATH}); run python -m paper_2510_27351_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.wf_forward.argtypes = [ctypes.c_int, i64, i64, p, i64, p, i64, p, p, i32, p]
+    lib.wf_forward.restype = ctypes.c_int
+    lib.wf_ckpt_elems.argtypes = [i64, i64, i32]
+    lib.wf_ckpt_elems.restype = i64
+    lib.wf_set_tile.argtypes = [i32]
+    lib.wf_set_tile.restype = ctypes.c_int
+    lib.wf_last_async_error.argtypes = [p]
+    lib.wf_last_async_error.restype = ctypes.c_int
+    lib.wf_error_string.argtypes = [ctypes.c_int]
+    lib.wf_error_string.restype = ctypes.c_char_p
+    lib.wf_version.argtypes = []
+    lib.wf_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def error_string(code: int) -> str:
+    return load().wf_error_string(code).decode()
+
+
+def check(code: int, what: str) -> None:
+    if code != WF_OK:
+        raise WfError(code, what)
+
+
+def declared_symbols(header: str = HEADER) -> list[str]:
+    """Names of the functions declared in include/wf.h."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wf_[a-z_0-9]+)\s*\(", text)))

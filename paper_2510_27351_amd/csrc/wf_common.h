@@ -1,0 +1,198 @@
+// Device-side building blocks shared by the libwf sweep kernels (gfx950, wave64).
+//
+// Cell operation (reading R0 of the west / north / north-west recurrence; the paper states
+// no recurrence, see include/wf.h):  D = C + min(NW, N, W).  The min is exact in every
+// element type, and the float/double add rounds once, so any schedule reproduces the
+// row-by-row result value for value.
+#pragma once
+
+#include "wf_internal.h"
+
+namespace wf {
+
+// ---------------------------------------------------------------------------------------
+// Element traits.  'W' is the number of 32-bit payload words per element in the tagged
+// handoff words; RING is the per-row length (in elements) of the LDS ring of a band and
+// PITCH its row pitch, chosen so that the byte pitch is 16 mod 256: a 16-byte read by each
+// lane of a different row then hits distinct LDS banks.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct Elem;
+
+__device__ __forceinline__ uint32_t dpp_shr1_u32(uint32_t src, uint32_t old) {
+  // wave_shr:1 -- lane r receives lane r-1's value; lane 0 keeps 'old' (bound_ctrl off).
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xf, 0xf, false);
+}
+
+template <>
+struct Elem<float> {
+  static constexpr int W = 1;
+  static constexpr int RING = 512;
+  static constexpr int PITCH = RING + 4;
+  __device__ static __forceinline__ float inf() { return __builtin_inff(); }
+  __device__ static __forceinline__ float zero() { return 0.0f; }
+  __device__ static __forceinline__ float shr1(float src, float old) {
+    return __builtin_bit_cast(float, dpp_shr1_u32(__builtin_bit_cast(uint32_t, src),
+                                                  __builtin_bit_cast(uint32_t, old)));
+  }
+  __device__ static __forceinline__ float min3(float a, float b, float c) {
+    return __builtin_fminf(__builtin_fminf(a, b), c);
+  }
+  __device__ static __forceinline__ float add(float c, float v) { return c + v; }
+  __device__ static __forceinline__ uint32_t word(float x, int) { return __builtin_bit_cast(uint32_t, x); }
+  __device__ static __forceinline__ float from_words(const uint32_t* w) { return __builtin_bit_cast(float, w[0]); }
+};
+
+template <>
+struct Elem<int32_t> {
+  static constexpr int W = 1;
+  static constexpr int RING = 512;
+  static constexpr int PITCH = RING + 4;
+  __device__ static __forceinline__ int32_t inf() { return 0x7fffffff; }
+  __device__ static __forceinline__ int32_t zero() { return 0; }
+  __device__ static __forceinline__ int32_t shr1(int32_t src, int32_t old) {
+    return (int32_t)dpp_shr1_u32((uint32_t)src, (uint32_t)old);
+  }
+  __device__ static __forceinline__ int32_t min3(int32_t a, int32_t b, int32_t c) {
+    int32_t x = a < b ? a : b;
+    return x < c ? x : c;
+  }
+  // Saturating, so that +inf (INT32_MAX) stays +inf on the virtual border; real cells
+  // never saturate under the documented bound on |C|.
+  __device__ static __forceinline__ int32_t add(int32_t c, int32_t v) { return __builtin_elementwise_add_sat(c, v); }
+  __device__ static __forceinline__ uint32_t word(int32_t x, int) { return (uint32_t)x; }
+  __device__ static __forceinline__ int32_t from_words(const uint32_t* w) { return (int32_t)w[0]; }
+};
+
+template <>
+struct Elem<double> {
+  static constexpr int W = 2;
+  static constexpr int RING = 256;
+  static constexpr int PITCH = RING + 2;
+  __device__ static __forceinline__ double inf() { return __builtin_inf(); }
+  __device__ static __forceinline__ double zero() { return 0.0; }
+  __device__ static __forceinline__ double shr1(double src, double old) {
+    uint64_t s = __builtin_bit_cast(uint64_t, src), o = __builtin_bit_cast(uint64_t, old);
+    uint32_t lo = dpp_shr1_u32((uint32_t)s, (uint32_t)o);
+    uint32_t hi = dpp_shr1_u32((uint32_t)(s >> 32), (uint32_t)(o >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  }
+  __device__ static __forceinline__ double min3(double a, double b, double c) {
+    return __builtin_fmin(__builtin_fmin(a, b), c);
+  }
+  __device__ static __forceinline__ double add(double c, double v) { return c + v; }
+  __device__ static __forceinline__ uint32_t word(double x, int k) {
+    uint64_t b = __builtin_bit_cast(uint64_t, x);
+    return k == 0 ? (uint32_t)b : (uint32_t)(b >> 32);
+  }
+  __device__ static __forceinline__ double from_words(const uint32_t* w) {
+    return __builtin_bit_cast(double, ((uint64_t)w[1] << 32) | w[0]);
+  }
+};
+
+// Four consecutive elements, as moved by one 16-byte (float/int) or two 16-byte (double)
+// LDS accesses.
+template <typename T>
+struct alignas(16) Vec4 {
+  T v[4];
+};
+
+// ---------------------------------------------------------------------------------------
+// Synchronisation helpers.
+//
+// Inside a workgroup the four waves hand sub-chunks to each other through LDS counters: a
+// producer writes its data to LDS, waits for those writes (lgkmcnt) and then stores the
+// counter; a consumer spins on the counter.  Nothing here waits on global-memory counters,
+// so the loader's prefetches stay in flight.
+//
+// Between workgroups, boundary values travel as 64-bit words (32 payload bits, 32 tag
+// bits) stored and loaded with agent-scope relaxed atomics; a word is valid when its tag
+// equals the launch epoch.  Each word validates itself, so no fences and no flag ordering
+// are needed, and a stale word from an earlier launch can never be mistaken for a new one.
+//
+// Every wait is bounded: after kSpinTicks of the 100 MHz real-time counter (2 s) it records
+// kErrTimeout, raises the workspace abort flag and gives up; every other wait then gives up
+// at its next poll.  The outputs of such a launch are undefined but the kernel terminates.
+// ---------------------------------------------------------------------------------------
+constexpr uint64_t kSpinTicks = 200000000ull;
+
+__device__ __forceinline__ void lds_wait_writes() { __builtin_amdgcn_s_waitcnt(0xC07F); }  // lgkmcnt(0) only
+
+__device__ __forceinline__ uint32_t lds_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_publish(uint32_t* p, uint32_t v) {
+  lds_wait_writes();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ bool global_aborted(const Control* ctl) {
+  return __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+}
+
+__device__ __forceinline__ void raise_timeout(Control* ctl) {
+  __hip_atomic_fetch_or(&ctl->err, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave-uniform wait until *p >= need.  Returns false if the launch is being aborted.
+__device__ __forceinline__ bool lds_wait_ge(const uint32_t* p, uint32_t need, uint32_t* lds_abort,
+                                            Control* ctl) {
+  if (lds_load(p) >= need) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return true;
+  }
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  uint32_t polls = 0;
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    if (lds_load(p) >= need) break;
+    if ((++polls & 255u) == 0u) {
+      if (lds_load(lds_abort) != 0u || global_aborted(ctl)) return false;
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) {
+        raise_timeout(ctl);
+        return false;
+      }
+    }
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return true;
+}
+
+__device__ __forceinline__ uint64_t tagged(uint32_t payload, uint32_t epoch) {
+  return ((uint64_t)epoch << 32) | payload;
+}
+__device__ __forceinline__ void store_word(uint64_t* p, uint64_t w) {
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_word(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claims the next work index for the whole workgroup (thread 0 claims, LDS broadcasts).
+// Also snapshots the abort flag so that the loop exit is uniform across the workgroup.
+__device__ __forceinline__ void claim_next(Control* ctl, uint32_t* sh_item, uint32_t* sh_abort) {
+  if (threadIdx.x == 0) {
+    *sh_item = __hip_atomic_fetch_add(&ctl->claim, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (global_aborted(ctl)) *sh_abort = 1u;
+  }
+  __syncthreads();
+}
+
+// Last workgroup out resets the control block for the next launch.
+__device__ __forceinline__ void finish_launch(Control* ctl, uint32_t epoch) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t d = __hip_atomic_fetch_add(&ctl->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (d == gridDim.x - 1) {
+      __hip_atomic_store(&ctl->claim, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->abort, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t next = epoch + 1u;
+      __hip_atomic_store(&ctl->epoch, next == 0u ? 1u : next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+}  // namespace wf
