@@ -20,10 +20,12 @@
  *   Adjoint.  For the loss  L = sum(gD * D) + gscore * score  and a fixed SEL, the routed
  *   (sub)gradient A = dL/dD = dL/dC is, in reverse row-major order,
  *       A[i][j] = gD[i][j] + [i==m-1 && j==n-1] * gscore
- *               + [SEL[i+1][j]   == N ] * A[i+1][j]
- *               + [SEL[i][j+1]   == W ] * A[i][j+1]
  *               + [SEL[i+1][j+1] == NW] * A[i+1][j+1]
- *   summed in exactly that order, and gC = A.
+ *               + [SEL[i][j+1]   == W ] * A[i][j+1]
+ *               + [SEL[i+1][j]   == N ] * A[i+1][j]
+ *   summed left to right in exactly that order, and gC = A.  (The order of the three
+ *   routed terms is a reading: the paper gives none.  This one adds the term known
+ *   earliest in a reverse anti-diagonal sweep first.)
  *
  * Precision: the f64 forms accumulate in double (inputs may be float data widened to
  * double, so input quantisation is not counted as error); the f32 forms perform exactly one
@@ -100,10 +102,10 @@ void wfo_forward_i64(int64_t m, int64_t n, const int64_t* C, int64_t ldc, int64_
       for (int64_t j = n - 1; j >= 0; --j) {                                               \
         T a = gD ? gD[i * ldgd + j] : (T)0;                                                \
         if (i == m - 1 && j == n - 1) a = a + gscore;                                      \
-        if (i + 1 < m && sel[(i + 1) * n + j] == WFO_SEL_N) a = a + gC[(i + 1) * ldgc + j]; \
-        if (j + 1 < n && sel[i * n + (j + 1)] == WFO_SEL_W) a = a + gC[i * ldgc + (j + 1)]; \
         if (i + 1 < m && j + 1 < n && sel[(i + 1) * n + (j + 1)] == WFO_SEL_NW)            \
           a = a + gC[(i + 1) * ldgc + (j + 1)];                                            \
+        if (j + 1 < n && sel[i * n + (j + 1)] == WFO_SEL_W) a = a + gC[i * ldgc + (j + 1)]; \
+        if (i + 1 < m && sel[(i + 1) * n + j] == WFO_SEL_N) a = a + gC[(i + 1) * ldgc + j]; \
         gC[i * ldgc + j] = a;                                                              \
       }                                                                                    \
     }                                                                                      \
