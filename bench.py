@@ -1,19 +1,25 @@
 """Benchmark of the wavefront sweep on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384] [--no-cpu] [--calib-copy]
 
-Default workload: one 16384 x 16384 float32 instance, values normal(0,1) clipped to
-[-4, 4] (seed 2), resident in HBM before timing.  A step is one forward sweep producing
-the full table D and the score.  Prints ONE JSON line with cells/s, the effective HBM rate
-(3 m n sizeof(elem) per sweep), the algorithmic rate, the forward kernel's roofline entry
-measured with HIP events on the launch stream, and the CPU oracle timed on a bounded
-sample on this host.
+Workload: one 16384 x 16384 float32 instance, values normal(0,1) clipped to [-4, 4]
+(seed 2), resident in HBM before timing.  A step is the whole differentiable sweep:
+  1. wf_forward: the table D, the score and the checkpoint grid (band rows every 64 rows,
+     block columns every K = 64 columns), one persistent kernel;
+  2. wf_backward from that checkpoint grid with g_score = 1 (the score's gradient): the
+     selection recompute kernel and the reverse adjoint kernel.
+Prints ONE JSON line: cells/s of the step (value), per-sweep cells/s and effective HBM
+rates (3 m n sizeof(elem) per sweep, 6 m n sizeof(elem) per step), the roofline entry of
+the forward kernel measured with HIP events on its launch stream, and the CPU oracle timed
+on a bounded sample on this host.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -21,6 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0  # MI355X published HBM3E bandwidth
+CKPT_K = 64
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel_f32_16384_traffic.txt")
+FWD_SOURCES = ["wf_fwd.hip", "wf_common.h", "wf_internal.h"]
 
 
 def parse():
@@ -30,38 +39,64 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=16384)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="first run one plain device copy of m*n elements (HBM counter calibration)")
     return p.parse_args()
 
 
-def cpu_baseline(C_cpu, budget_s: float = 12.0):
-    """Times the CPU oracle (single-threaded C, float64) on a bounded leading block of the
-    same matrix: the top-left r x r block, r chosen to take roughly 'budget_s'."""
+def fwd_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in FWD_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_27351_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per forward launch from the committed counter summary, or None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    src = re.search(r"^source_hash:\s*(\S+)", text, re.M)
+    val = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not src or not val or src.group(1) != fwd_source_hash():
+        return None
+    return float(val.group(1))
+
+
+def cpu_baseline(C_cpu, budget_s: float = 15.0):
+    """Times the CPU oracle (single-threaded C, float64, row by row) on a bounded leading
+    block of the same matrix: forward with the selection map, then the adjoint of the score.
+    The block edge is grown from a probe so that the timed call takes about budget_s."""
     import numpy as np
 
     import oracle
     oracle.build(force=False)
     n = C_cpu.shape[0]
-    r = min(n, 2048)
-    block = C_cpu[:r, :r].numpy().astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.forward(block, "f64", want_sel=False)
-    dt = time.perf_counter() - t0
-    reps = max(1, int(budget_s / max(dt, 1e-3)))
-    # grow the block to use the budget in one call when possible
+
+    def run(r):
+        block = C_cpu[:r, :r].numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        _, sel = oracle.forward(block, "f64", want_sel=True)
+        oracle.backward(sel, None, 1.0, "f64")
+        return time.perf_counter() - t0
+
+    r = min(n, 1024)
+    dt = run(r)
     r2 = int(min(n, r * max(1.0, (budget_s / max(dt, 1e-3)) ** 0.5)))
-    block = C_cpu[:r2, :r2].numpy().astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.forward(block, "f64", want_sel=False)
-    dt = time.perf_counter() - t0
-    del reps
+    dt = run(r2)
     return {"value": r2 * r2 / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"top-left {r2}x{r2} block of the same matrix, row-by-row f64 C oracle, one call, {dt:.2f} s"}
+            "sample": f"top-left {r2}x{r2} block of the same matrix; f64 row-by-row C oracle, "
+                      f"forward with selection map then adjoint of the score, one thread, {dt:.2f} s"}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this build measures one GPU only (one process, one device); "
+                                   "run with --gpus 1"}))
         sys.exit(2)
     import torch
 
@@ -70,43 +105,68 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    n = args.n
+    n = m = args.n
     C_cpu = inputs.single_16384_f32(n)
     C = C_cpu.to(dev)
     D = torch.empty_like(C)
-    m = n
+    gC = torch.empty_like(C)
+    one = torch.ones((), dtype=C.dtype, device=dev)
+    ckpt = torch.empty(wf.ckpt_elems(m, n, CKPT_K), dtype=C.dtype, device=dev)
     stream = torch.cuda.current_stream(dev)
+    lib = wf._lib.load()
+    code = wf._lib.WF_F32
+    sp = stream.cuda_stream
+
+    def fwd():
+        wf._lib.check(lib.wf_forward(code, m, n, C.data_ptr(), n, D.data_ptr(), n, wf_score.data_ptr(),
+                                     ckpt.data_ptr(), CKPT_K, sp), "wf_forward")
+
+    def bwd():
+        wf._lib.check(lib.wf_backward(code, m, n, C.data_ptr(), n, ckpt.data_ptr(), CKPT_K, None, n,
+                                      one.data_ptr(), None, n, gC.data_ptr(), n, sp), "wf_backward")
+
+    wf_score = torch.empty((), dtype=C.dtype, device=dev)
+    if args.calib_copy:
+        D.copy_(C)
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
-        wf.forward(C, D=D)
+        fwd()
+        bwd()
     wf.last_async_error()
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
-    for k in range(args.steps):
-        ev[2 * k].record(stream)
-        wf.forward(C, D=D)
-        ev[2 * k + 1].record(stream)
+    for k in range(K):
+        ev[k][0].record(stream)
+        fwd()
+        ev[k][1].record(stream)
+        bwd()
+        ev[k][2].record(stream)
     t_end.record(stream)
     torch.cuda.synchronize()
     wf.last_async_error()
     total_ms = t_start.elapsed_time(t_end)
-    per = [ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]
-    ms = total_ms / args.steps
-    kern_ms = sum(per) / len(per)
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    bwd_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    ms = total_ms / K
     cells = m * n
     es = C.element_size()
-    alg_bytes = 2 * cells * es  # read C, write D
-    eff_bytes = 3 * cells * es
-    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    ck_bytes = ckpt.numel() * es
+    # algorithmic bytes per launch of the forward kernel: read C, write D and the grid
+    fwd_alg = 2 * cells * es + ck_bytes
+    achieved = fwd_alg / (fwd_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    eff = lambda nbytes, t_ms: nbytes / (t_ms * 1e-3) / 1e9  # noqa: E731
     out = {
         "metric": "cells/sec and effective HBM GB/s (% peak), fwd and fwd+adjoint, n=16384",
         "value": cells / (ms * 1e-3),
         "unit": "cells/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
@@ -114,19 +174,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"single {m}x{n} float32 normal(0,1) clipped to [-4,4], seed 2; "
-                               "step = forward sweep writing D and the score",
-                   "m": m, "n": n},
-        "effective_GBps": eff_bytes / (ms * 1e-3) / 1e9,
-        "effective_pct_peak": 100.0 * eff_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
-        "algorithmic_GBps": alg_bytes / (ms * 1e-3) / 1e9,
+        "config": {"workload": f"single {m}x{n} float32, normal(0,1) clipped to [-4,4], seed 2; step = "
+                               f"forward (table, score, checkpoint grid K={CKPT_K}) + adjoint of the score "
+                               "from the checkpoint grid",
+                   "m": m, "n": n, "ckpt_k": CKPT_K},
+        "fwd": {"ms": fwd_ms, "cells_per_s": cells / (fwd_ms * 1e-3),
+                "effective_GBps": eff(3 * cells * es, fwd_ms),
+                "effective_pct_peak": 100 * eff(3 * cells * es, fwd_ms) / PEAK_HBM_GBPS},
+        "adjoint": {"ms": bwd_ms, "cells_per_s": cells / (bwd_ms * 1e-3),
+                    "effective_GBps": eff(3 * cells * es, bwd_ms),
+                    "effective_pct_peak": 100 * eff(3 * cells * es, bwd_ms) / PEAK_HBM_GBPS},
+        "fwd_adjoint": {"ms": ms, "effective_GBps": eff(6 * cells * es, ms),
+                        "effective_pct_peak": 100 * eff(6 * cells * es, ms) / PEAK_HBM_GBPS},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBPS, "traffic": None,
-                     "kernel": "fwd_kernel<float,64>", "kernel_ms": kern_ms,
-                     "bytes_per_launch": alg_bytes},
+                     "frac": achieved / PEAK_HBM_GBPS,
+                     "traffic": traffic,
+                     "kernel": "fwd_kernel<float,64,1>", "kernel_ms": fwd_ms,
+                     "bytes_per_launch": fwd_alg},
     }
     if not args.no_cpu:
-        del D
+        del D, gC
         out["cpu_baseline"] = cpu_baseline(C_cpu)
     print(json.dumps(out), flush=True)
 

@@ -29,6 +29,8 @@
  *     allocates and synchronizes the device).  Calls that share a device must be ordered
  *     (one stream, or streams joined by events): two overlapping calls on one device race on
  *     that workspace.
+ *   - Leading dimensions are limited to (2^31 / 128 - 16) bytes (about 4.2 million float
+ *     columns): larger values return WF_E_UNSUPPORTED.
  *   - Element types: WF_F32 (float, one IEEE add per cell, min exact), WF_F64 (double),
  *     WF_I32 (int32; the caller guarantees (m+n-1) * max|C| < 2^31 - 1 so no sum overflows).
  *     Inputs must be free of NaN and -inf; +inf marks a blocked cell.
@@ -60,8 +62,8 @@ enum {
  *   D      [out] m x n table, leading dimension ldd >= n; NULL = score-only mode (the table
  *                is never written to memory; the sweep still runs over every cell).
  *   score  [out] one element, D[m-1][n-1].  Required.
- *   ckpt   [out] checkpoint grid for wf_backward, wf_ckpt_elems(m, n, ckpt_k) elements, or
- *                NULL when ckpt_k == 0.  Layout: first the band rows -- D[64b+63][0..n-1] for
+ *   ckpt   [out] checkpoint grid for wf_backward, wf_ckpt_elems(m, n, ckpt_k) elements; NULL
+ *                when ckpt_k == 0 (and allowed when that count is 0).  Layout: first the band rows -- D[64b+63][0..n-1] for
  *                b = 0 .. ceil(m/64)-2, row after row -- then the block columns --
  *                D[0..m-1][K q - 1] for q = 1 .. ceil(n/K)-1, column after column
  *                (K = ckpt_k).  Rows are every 64 because the device sweep works on bands of
@@ -77,11 +79,49 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
 int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k);
 
 /*
+ * Adjoint sweep: writes g_C = dL/dC for  L = sum(g_D * D) + g_score * score, where D and
+ * score are the forward results for C.  The derivative is the routed (sub)gradient of the
+ * min: each cell passes its adjoint to the one predecessor it selected (ties NW, N, W), so
+ * A[i][j] = g_D[i][j] + [i=m-1, j=n-1] g_score + [SEL(i+1,j+1)=NW] A[i+1][j+1]
+ *         + [SEL(i,j+1)=W] A[i][j+1] + [SEL(i+1,j)=N] A[i+1][j]   (summed in that order)
+ * and g_C = A.  The selections are recomputed on the device from the input and either the
+ * checkpoint grid of wf_forward (its band rows; pass ckpt_k > 0 and D = NULL) or the saved
+ * table D (pass ckpt = NULL, ckpt_k = 0).
+ *   dtype       WF_F32 or WF_F64 (WF_I32 returns WF_E_UNSUPPORTED).
+ *   C, ldc      the forward input, m x n.
+ *   ckpt, ckpt_k  the checkpoint grid and K of the forward call, or NULL / 0 (ckpt may be
+ *               NULL with ckpt_k > 0 when the grid is empty, i.e. m <= 64 and n <= K).
+ *   D, ldd      the forward table, or NULL.
+ *   g_score     one element, or NULL for 0.
+ *   g_D, ldgd   m x n upstream gradient of the table, or NULL for 0.
+ *   g_C, ldgc   m x n output.
+ * Uses (and grows) the device workspace: 2 bits per cell for the selections plus handoff
+ * words.  Results are bitwise reproducible; in float the sums round once per term in the
+ * order above.
+ */
+int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt,
+                int32_t ckpt_k, const void* D, int64_t ldd, const void* g_score, const void* g_D,
+                int64_t ldgd, void* g_C, int64_t ldgc, void* stream);
+
+/*
  * Force the tile width (columns per handoff unit, 64 rows per band) used by later calls on
  * this process: 16, 32 or 64, or 0 to return to the automatic choice.  Returns WF_E_ARG for
  * any other value.  Used by the autotuner and the tests.
  */
 int wf_set_tile(int32_t tile);
+
+/*
+ * Tracing (for profiling the pipeline, off by default).  wf_trace_enable(B) allocates a
+ * device buffer of B records on the current device; later forward calls on that device
+ * whose band count is <= B fill record b for band b (a later call overwrites earlier
+ * records).  wf_trace_enable(0) frees it.  wf_trace_fetch synchronizes the device and
+ * copies up to max_bands records (8 uint64 each: claim time, first sub-chunk ready,
+ * compute done, store done -- 100 MHz ticks --, sub-chunks the compute wave found not yet
+ * loaded, sub-chunks whose top row had not yet arrived, XCC id, workgroup id) into 'host';
+ * it returns the number of records copied, or minus an error code.
+ */
+int wf_trace_enable(int64_t max_bands);
+int64_t wf_trace_fetch(uint64_t* host, int64_t max_bands);
 
 /*
  * Synchronizes 'stream', then reports and clears the device-side error state of the

@@ -15,7 +15,8 @@ import torch
 from . import _lib
 from ._lib import WfError  # noqa: F401
 
-__all__ = ["forward", "ckpt_elems", "set_tile", "last_async_error", "WfError", "BAND"]
+__all__ = ["forward", "backward", "sweep", "WfFunction", "ckpt_elems", "set_tile", "last_async_error",
+           "WfError", "BAND"]
 
 BAND = 64  # rows per band of the device sweep (= wavefront size)
 
@@ -66,10 +67,86 @@ def forward(C: torch.Tensor, table: bool = True, ckpt_k: int = 0, D: torch.Tenso
         ckpt = torch.empty(ckpt_elems(m, n, ckpt_k), dtype=C.dtype, device=C.device)
     rc = lib.wf_forward(_dtype_code(C), m, n, C.data_ptr(), C.stride(0),
                         D.data_ptr() if D is not None else None, D.stride(0) if D is not None else n,
-                        score.data_ptr(), ckpt.data_ptr() if ckpt is not None else None, ckpt_k,
+                        score.data_ptr(), (ckpt.data_ptr() or None) if ckpt is not None else None, ckpt_k,
                         _stream(C.device))
     _lib.check(rc, "wf_forward")
     return D, score, ckpt
+
+
+def backward(C: torch.Tensor, g_score: torch.Tensor | None = None, g_D: torch.Tensor | None = None,
+             ckpt: torch.Tensor | None = None, ckpt_k: int = 0, D: torch.Tensor | None = None,
+             g_C: torch.Tensor | None = None) -> torch.Tensor:
+    """Adjoint sweep: returns g_C = dL/dC for L = sum(g_D * D) + g_score * score.
+
+    The selections are recomputed on the device from C and either the checkpoint grid of
+    forward(C, ckpt_k=K) (pass ckpt and ckpt_k=K) or the saved table D (exactly one)."""
+    _check_matrix(C)
+    lib = _lib.load()
+    m, n = C.shape
+    if (ckpt is None) == (D is None) or (ckpt is not None and ckpt_k < 1):
+        raise ValueError("pass exactly one of ckpt (with ckpt_k) or D")
+    for name, t in (("g_D", g_D), ("D", D), ("g_C", g_C)):
+        if t is not None and (t.shape != (m, n) or t.dtype != C.dtype or t.device != C.device
+                              or t.stride(1) != 1):
+            raise ValueError(f"{name} must match C's shape, dtype and device, row-major")
+    if ckpt is not None:
+        if ckpt.dtype != C.dtype or ckpt.device != C.device or not ckpt.is_contiguous() \
+                or ckpt.numel() != ckpt_elems(m, n, ckpt_k):
+            raise ValueError("ckpt must be the checkpoint grid of forward(C, ckpt_k=ckpt_k)")
+    if g_score is not None:
+        g_score = g_score.to(device=C.device, dtype=C.dtype).reshape(()).contiguous()
+    if g_C is None:
+        g_C = torch.empty((m, n), dtype=C.dtype, device=C.device)
+    rc = lib.wf_backward(_dtype_code(C), m, n, C.data_ptr(), C.stride(0),
+                         (ckpt.data_ptr() or None) if ckpt is not None else None,
+                         ckpt_k if ckpt is not None else 0,
+                         D.data_ptr() if D is not None else None, D.stride(0) if D is not None else n,
+                         g_score.data_ptr() if g_score is not None else None,
+                         g_D.data_ptr() if g_D is not None else None, g_D.stride(0) if g_D is not None else n,
+                         g_C.data_ptr(), g_C.stride(0), _stream(C.device))
+    _lib.check(rc, "wf_backward")
+    return g_C
+
+
+class WfFunction(torch.autograd.Function):
+    """Differentiable sweep: (D, score) = sweep(C), gradient by the adjoint sweep.
+
+    With table=False only the score is produced and the forward keeps the band rows of the
+    checkpoint grid (m/64 rows of n elements) instead of the table; with table=True the
+    table is saved and the backward recomputes the selections from it."""
+
+    @staticmethod
+    def forward(ctx, C: torch.Tensor, table: bool):
+        C = C.contiguous()
+        m, n = C.shape
+        if table:
+            D, score, _ = forward(C, table=True)
+            ctx.save_for_backward(C, D)
+            ctx.mode = "table"
+            return D, score
+        k = min(max(n, 1), 4096)
+        _, score, ckpt = forward(C, table=False, ckpt_k=k)
+        ctx.save_for_backward(C, ckpt)
+        ctx.mode = "ckpt"
+        ctx.ckpt_k = k
+        return score
+
+    @staticmethod
+    def backward(ctx, *grads):
+        C, saved = ctx.saved_tensors
+        if ctx.mode == "table":
+            g_D, g_score = grads
+            g_D = None if g_D is None else g_D.contiguous()
+            g_C = backward(C, g_score=g_score, g_D=g_D, D=saved)
+        else:
+            (g_score,) = grads
+            g_C = backward(C, g_score=g_score, ckpt=saved, ckpt_k=ctx.ckpt_k)
+        return g_C, None
+
+
+def sweep(C: torch.Tensor, table: bool = False):
+    """Autograd entry point: score (table=False) or (D, score) (table=True)."""
+    return WfFunction.apply(C, table)
 
 
 def set_tile(tile: int) -> None:

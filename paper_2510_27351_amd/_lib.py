@@ -32,6 +32,8 @@ def load():
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.wf_forward.argtypes = [ctypes.c_int, i64, i64, p, i64, p, i64, p, p, i32, p]
     lib.wf_forward.restype = ctypes.c_int
+    lib.wf_backward.argtypes = [ctypes.c_int, i64, i64, p, i64, p, i32, p, i64, p, p, i64, p, i64, p]
+    lib.wf_backward.restype = ctypes.c_int
     lib.wf_ckpt_elems.argtypes = [i64, i64, i32]
     lib.wf_ckpt_elems.restype = i64
     lib.wf_set_tile.argtypes = [i32]
@@ -40,6 +42,10 @@ def load():
     lib.wf_last_async_error.restype = ctypes.c_int
     lib.wf_error_string.argtypes = [ctypes.c_int]
     lib.wf_error_string.restype = ctypes.c_char_p
+    lib.wf_trace_enable.argtypes = [i64]
+    lib.wf_trace_enable.restype = ctypes.c_int
+    lib.wf_trace_fetch.argtypes = [p, i64]
+    lib.wf_trace_fetch.restype = i64
     lib.wf_version.argtypes = []
     lib.wf_version.restype = ctypes.c_int
     _lib = lib

@@ -22,12 +22,18 @@ struct DeviceWs {
   Control* ctl = nullptr;     // device control block (zeroed, epoch = 1)
   uint64_t* bnd = nullptr;    // tagged handoff words
   size_t bnd_words = 0;
+  uint32_t* sel = nullptr;    // selection codes of the adjoint
+  size_t sel_words = 0;
   int num_cus = 0;
 };
 
 std::mutex g_mu;
 std::vector<DeviceWs> g_ws;
 int g_tile_override = 0;
+// optional per-band trace buffer (one, for the device that enabled it)
+uint64_t* g_trace = nullptr;
+int64_t g_trace_bands = 0;
+int g_trace_dev = -1;
 
 int ensure_ws(int dev, size_t words, DeviceWs** out) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -46,7 +52,7 @@ int ensure_ws(int dev, size_t words, DeviceWs** out) {
   if (words > w.bnd_words) {
     // Growing: the old buffer may still be read by queued work, so drain the device first.
     if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
-    if (w.bnd) hipFree(w.bnd);
+    if (w.bnd) (void)hipFree(w.bnd);
     w.bnd = nullptr;
     w.bnd_words = 0;
     size_t bytes = words * sizeof(uint64_t);
@@ -57,6 +63,19 @@ int ensure_ws(int dev, size_t words, DeviceWs** out) {
     w.bnd_words = words;
   }
   *out = &w;
+  return WF_OK;
+}
+
+// Grows the adjoint's selection buffer of a workspace that ensure_ws has set up.
+int ensure_sel(DeviceWs* w, size_t words) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (words <= w->sel_words) return WF_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+  if (w->sel) (void)hipFree(w->sel);
+  w->sel = nullptr;
+  w->sel_words = 0;
+  if (hipMalloc(&w->sel, words * sizeof(uint32_t)) != hipSuccess) { w->sel = nullptr; return WF_E_NOMEM; }
+  w->sel_words = words;
   return WF_OK;
 }
 
@@ -83,6 +102,10 @@ int choose_tile(int64_t m, int64_t n) {
 }
 
 int64_t nbands(int64_t m) { return (m + kBand - 1) / kBand; }
+
+// Largest leading dimension, in bytes: a band of up to 128 rows is addressed with 32-bit
+// byte offsets.
+constexpr int64_t kMaxLd = ((int64_t)1 << 31) / 128 - 16;
 
 }  // namespace
 }  // namespace wf
@@ -129,9 +152,13 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
   if (!C || !score || ldc < n) return WF_E_ARG;
   if (D && ldd < n) return WF_E_ARG;
   if (ckpt_k < 0 || ckpt_k > 4096) return WF_E_ARG;
-  if ((ckpt_k > 0) != (ckpt != nullptr)) return WF_E_ARG;
+  if (ckpt_k == 0 && ckpt != nullptr) return WF_E_ARG;
+  if (ckpt_k > 0 && ckpt == nullptr && wf_ckpt_elems(m, n, ckpt_k) > 0) return WF_E_ARG;
   if ((m - 1) > INT64_MAX / ldc) return WF_E_ARG;
-  const int64_t nb = nbands(m);
+  // a band of 64 rows is addressed with 32-bit byte offsets
+  if (ldc > kMaxLd / es || (D && ldd > kMaxLd / es)) return WF_E_UNSUPPORTED;
+  const int64_t band_rows = forward_band_rows(dtype);
+  const int64_t nb = (m + band_rows - 1) / band_rows;
   if (nb > 0x7fffffff) return WF_E_ARG;
 
   int dev = 0;
@@ -154,10 +181,114 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
   a.nb = (int32_t)nb;
   a.ctl = ws->ctl;
   a.bnd = ws->bnd;
+  a.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
   const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
   const int tile = choose_tile(m, n);
   hipError_t e = launch_forward(dtype, tile, a, grid, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
+}
+
+int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt, int32_t ckpt_k,
+                const void* D, int64_t ldd, const void* g_score, const void* g_D, int64_t ldgd, void* g_C,
+                int64_t ldgc, void* stream) {
+  if (dtype != WF_F32 && dtype != WF_F64) return dtype == WF_I32 ? WF_E_UNSUPPORTED : WF_E_ARG;
+  const int es = elem_size(dtype);
+  if (m < 1 || n < 1 || n > (int64_t)1 << 31 || m > (int64_t)1 << 40) return WF_E_ARG;
+  if (m > INT64_MAX / n) return WF_E_ARG;
+  if (!C || !g_C || ldc < n || ldgc < n) return WF_E_ARG;
+  if (g_D && ldgd < n) return WF_E_ARG;
+  // exactly one source of the band top rows: the checkpoint grid (ckpt_k > 0) or the table
+  if (ckpt_k < 0 || ckpt_k > 4096) return WF_E_ARG;
+  if (ckpt_k > 0) {
+    if (D != nullptr) return WF_E_ARG;
+    if (ckpt == nullptr && wf_ckpt_elems(m, n, ckpt_k) > 0) return WF_E_ARG;
+  } else {
+    if (D == nullptr || ckpt != nullptr || ldd < n) return WF_E_ARG;
+  }
+  if (ldc > kMaxLd / es || ldgc > kMaxLd / es || (g_D && ldgd > kMaxLd / es)) return WF_E_UNSUPPORTED;
+  const int64_t nb = nbands(m);
+  if (nb > 0x7fffffff) return WF_E_ARG;
+  const int64_t Ks = (n + kBand - 1 + 63) / 64;
+  if (Ks > 0x7fffffff / 64) return WF_E_ARG;
+
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  const size_t words = (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * 2 * words_per_elem(dtype);
+  DeviceWs* ws = nullptr;
+  int rc = ensure_ws(dev, words, &ws);
+  if (rc != WF_OK) return rc;
+  rc = ensure_sel(ws, (size_t)nb * (size_t)Ks * 64 * 4);
+  if (rc != WF_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
+
+  SelArgs sa;
+  sa.C = C;
+  sa.ldc = ldc;
+  if (ckpt_k > 0) {  // band rows of the checkpoint grid: row 64b+63 is ckpt row b
+    sa.top = ckpt;
+    sa.ld_top = n;
+  } else {     // rows 64b+63 of the saved table
+    sa.top = static_cast<const char*>(D) + (size_t)63 * ldd * es;
+    sa.ld_top = 64 * ldd;
+  }
+  sa.m = m;
+  sa.n = n;
+  sa.nb = (int32_t)nb;
+  sa.Q = (int32_t)(4 * Ks);
+  sa.sel = ws->sel;
+  sa.ctl = ws->ctl;
+  hipError_t e = launch_select(dtype, sa, grid, st);
+  if (e != hipSuccess) return WF_E_DEVICE;
+
+  AdjArgs aa;
+  aa.sel = ws->sel;
+  aa.gD = g_D;
+  aa.gscore = g_score;
+  aa.gC = g_C;
+  aa.ldgd = g_D ? ldgd : n;
+  aa.ldgc = ldgc;
+  aa.m = m;
+  aa.n = n;
+  aa.nb = (int32_t)nb;
+  aa.Q = (int32_t)(4 * Ks);
+  aa.ctl = ws->ctl;
+  aa.bnd = ws->bnd;
+  aa.trace = nullptr;
+  e = launch_adjoint(dtype, choose_tile(m, n), aa, grid, st);
+  return e == hipSuccess ? WF_OK : WF_E_DEVICE;
+}
+
+int wf_trace_enable(int64_t max_bands) {
+  if (max_bands < 0 || max_bands > ((int64_t)1 << 32)) return WF_E_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_trace) {
+    if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+    (void)hipFree(g_trace);
+    g_trace = nullptr;
+    g_trace_bands = 0;
+    g_trace_dev = -1;
+  }
+  if (max_bands == 0) return WF_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  const size_t bytes = (size_t)max_bands * kTraceWords * sizeof(uint64_t);
+  if (hipMalloc(&g_trace, bytes) != hipSuccess) { g_trace = nullptr; return WF_E_NOMEM; }
+  if (hipMemset(g_trace, 0, bytes) != hipSuccess) return WF_E_DEVICE;
+  g_trace_bands = max_bands;
+  g_trace_dev = dev;
+  return WF_OK;
+}
+
+int64_t wf_trace_fetch(uint64_t* host, int64_t max_bands) {
+  if (!host || max_bands < 0) return -WF_E_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_trace) return 0;
+  const int64_t k = std::min(max_bands, g_trace_bands);
+  if (hipDeviceSynchronize() != hipSuccess) return -WF_E_DEVICE;
+  if (hipMemcpy(host, g_trace, (size_t)k * kTraceWords * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return -WF_E_DEVICE;
+  return k;
 }
 
 int wf_last_async_error(void* stream) {

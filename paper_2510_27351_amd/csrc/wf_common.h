@@ -137,27 +137,53 @@ __device__ __forceinline__ void raise_timeout(Control* ctl) {
 }
 
 // Wave-uniform wait until *p >= need.  Returns false if the launch is being aborted.
+// With check_global = false the wait never touches global memory (a global load would make
+// the wave wait for all of its outstanding loads): the loader uses that form and learns
+// of a global abort through the workgroup's LDS flag, which the other waves raise.
+// 'waited' accumulates the ticks spent spinning (for the optional trace); it is a
+// register-resident reference once inlined.
+template <bool check_global = true>
 __device__ __forceinline__ bool lds_wait_ge(const uint32_t* p, uint32_t need, uint32_t* lds_abort,
-                                            Control* ctl) {
+                                            Control* ctl, uint64_t& waited) {
   if (lds_load(p) >= need) {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return true;
   }
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   uint32_t polls = 0;
+  bool ok = true;
   for (;;) {
     __builtin_amdgcn_s_sleep(1);
     if (lds_load(p) >= need) break;
     if ((++polls & 255u) == 0u) {
-      if (lds_load(lds_abort) != 0u || global_aborted(ctl)) return false;
+      if (lds_load(lds_abort) != 0u || (check_global && global_aborted(ctl))) {
+        ok = false;
+        break;
+      }
       if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) {
         raise_timeout(ctl);
-        return false;
+        ok = false;
+        break;
       }
     }
   }
+  waited += __builtin_amdgcn_s_memrealtime() - t0;
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  return true;
+  return ok;
+}
+
+// Counter store for a wave whose earlier LDS writes must be seen first by the readers of
+// the counter.  LDS operations of one wave are performed in order, so the data written
+// before the counter is visible to any wave that has seen the counter; no wait is needed.
+__device__ __forceinline__ void lds_signal(uint32_t* p, uint32_t v) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Buffer resource over 'bytes' bytes at 'base' (raw, stride 0): loads beyond the range
+// return zero instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
 __device__ __forceinline__ uint64_t tagged(uint32_t payload, uint32_t epoch) {

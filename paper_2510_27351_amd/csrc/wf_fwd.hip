@@ -1,212 +1,382 @@
 // Persistent band-pipelined forward sweep (gfx950).
 //
-// Work decomposition.  The m x n table is cut into bands of 64 rows.  A persistent
+// Work decomposition.  The m x n table is cut into bands of H = 64*R rows.  A persistent
 // workgroup claims bands in increasing order from a device counter and sweeps each band
-// from left to right as a skewed wavefront: lane r of the compute wave owns band row r and,
-// at step t, produces column t - r, so the 64 cells of one step lie on one anti-diagonal.
-// The three inputs of a cell come from registers: W is the lane's previous value, N is the
-// previous value of lane r-1 moved by a DPP wave_shr:1, NW is the previous step's N.  Lane 0
-// takes N from the row above the band (the "top" ring in LDS), which the band above
-// published.  A band therefore takes n + 63 steps and the band below can follow 64 steps
-// (plus the handoff latency) behind: all m+n-1 anti-diagonals are processed by one launch.
+// from left to right as a skewed wavefront.  Lane r of the compute wave owns row r of each
+// of the band's R sub-bands of 64 rows (rows r, 64+r, ...).  Sub-band k runs 65*k steps
+// behind sub-band 0: at step t lane r produces column t - r - 65k of row 64k + r, so the
+// cells of one step lie on R anti-diagonals and all of a lane's chains are independent
+// within the step.  The three inputs of a cell come from registers:
+//   W  the lane's previous value in the same sub-band;
+//   N  the previous value of lane r-1 moved by a DPP wave_shr:1; lane 0 of sub-band 0 takes
+//      the row above the band (the "top" ring in LDS, published by the band above); lane 0
+//      of sub-band k >= 1 takes lane 63 of sub-band k-1 from two steps back, moved by a
+//      DPP wave_ror:1 one step ahead (the extra step of skew keeps that move off the chain);
+//   NW the previous step's N.
+// A band takes n + H + R - 2 steps and the band below trails it by H + R - 1 + G steps plus
+// the handoff latency: all m+n-1 anti-diagonals in one launch, with one handoff through
+// global memory per H rows.
 //
-// Inside a workgroup four waves split the work so that the compute wave issues little
-// besides its cell chain:
-//   wave 0  compute   per 4 steps: one 16-byte LDS read of C, one broadcast read of the top
-//                     boundary, 4 x (DPP shift, min3, add), one 16-byte LDS write of D;
-//   wave 1  loader    coalesced row-major global loads of C (16 bytes per lane), kept in
-//                     registers PF sub-chunks ahead, scattered into the skewed LDS ring;
-//   wave 2  top       polls the band above's tagged boundary words and fills the top ring;
-//   wave 3  storer    publishes the band's last row (tagged words) as soon as it is final,
-//                     writes D back coalesced, the checkpoint grid and the score.
-// The LDS ring stores element (r, c) at S[r][(r + c) mod RING]: all lanes touch the same
-// slot index at a given step, 16-byte reads/writes per lane are aligned, and the row pitch
-// (16 mod 256 bytes) keeps them free of bank conflicts.  D overwrites C in place.
+// Skewed LDS ring.  Element (row i, column c) of the band lives at S[i][(i + c + i/64) mod
+// RING]: at step t every lane touches slot t in every sub-band, so a lane's four
+// consecutive steps are one aligned 16-byte LDS access per sub-band.  A 16-byte chunk of
+// slots [4j, 4j+4) of row i holds four consecutive columns, which are also consecutive in
+// global memory, so every global transfer is one (4-byte aligned) 16-byte access paired
+// with one aligned 16-byte LDS access.  The row pitch is 16 mod 256 bytes, which keeps
+// 16-byte accesses of different rows on distinct banks.  D overwrites C in place.
 //
-// Sub-chunks of G columns ("tile width", 16/32/64) are the unit of every handoff.
+// Five waves per workgroup:
+//   wave 0  compute   per 4 steps and sub-band: one 16-byte LDS read of C, 4 x (DPP shift,
+//                     min3, add), one 16-byte LDS write of D; one broadcast read of the top;
+//   wave 1  loader    64-slot sub-chunks of C: 16R x (16-byte buffer load, 16-byte LDS write)
+//                     per lane, PF sub-chunks in flight in registers;
+//   wave 2  top       polls the band above's tagged boundary words, G columns at a time,
+//                     and fills the top ring;
+//   wave 3  storer    every 64 steps writes the sub-chunk's D back (16-byte LDS read,
+//                     16-byte global store), the checkpoint columns and the score;
+//   wave 4  publisher every G steps publishes the G newly final values of the band's last
+//                     row as tagged words for the band below, and the checkpoint rows.
+// The publisher has a wave of its own so that nothing delays the handoff, which sits on
+// the critical path of the whole sweep.  G (16/32/64, the "tile width") is the handoff
+// granularity.
 #include "wf_common.h"
 
 namespace wf {
 namespace {
 
-template <typename T, int G>
+constexpr int kSub = 64;  // slots per loader / storer sub-chunk
+
+// Returns x unchanged, but hides its value from the optimiser at this point.
+template <typename V>
+__device__ __forceinline__ V opaque(V x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
+__device__ __forceinline__ uint32_t dpp_ror1_u32(uint32_t src) {
+  // wave_ror:1 -- lane r receives lane r-1's value, lane 0 receives lane 63's.
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)src, 0x13C, 0xf, 0xf, false);
+}
+
+template <typename T>
+__device__ __forceinline__ T ror1(T x) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp_ror1_u32(__builtin_bit_cast(uint32_t, x)));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint64_t lo = dpp_ror1_u32((uint32_t)b), hi = dpp_ror1_u32((uint32_t)(b >> 32));
+    return __builtin_bit_cast(T, (hi << 32) | lo);
+  }
+}
+
+template <typename T, int G, int R>
 struct FwdCfg {
   using E = Elem<T>;
-  static constexpr int RING = E::RING;
-  static constexpr int PITCH = E::PITCH;
+  static constexpr int H = kBand * R;  // rows per band
+  // LDS ring: H rows x RING slots, about 128 KiB.
+  static constexpr int RING = (sizeof(T) == 4 ? 512 : 256) / R;
+  static constexpr int PITCH = RING + 16 / (int)sizeof(T);
   static constexpr int MASK = RING - 1;
-  static constexpr int VPR = G / 4;             // 4-element vectors per row per sub-chunk
-  static constexpr int VPL = (kBand * VPR) / 64; // vectors per lane per sub-chunk (= VPR)
-  // Sub-chunks the loader keeps in flight in registers (about 48 KiB per band).
-  static constexpr int PF = (48 * 1024) / (kBand * G * (int)sizeof(T)) < 1
-                                ? 1
-                                : (48 * 1024) / (kBand * G * (int)sizeof(T));
-  static_assert(RING % G == 0, "tile must divide the ring");
-  static_assert(RING >= 2 * G + kBand, "ring too small for the handoff distance");
+  // Sub-chunks the loader keeps in flight in registers (bounded by the 256 registers a wave
+  // may use when two of the five waves share a SIMD).
+  static constexpr int PF = sizeof(T) * R == 4 ? 2 : 1;
+  static constexpr int GPS = kSub / G;  // handoff units per sub-chunk
+  static constexpr int NG = G / 4;      // 4-step groups per unit
+  static_assert(RING % kSub == 0 && kSub % G == 0, "bad tiling");
+  static_assert(RING >= 4 * kSub, "ring too small");
+  // Offset between the column of row i at step t and t itself: column = t - i - i/64.
+  __device__ static __forceinline__ int skew(int i) { return i + i / kBand; }
 };
 
-struct Shared {
-  uint32_t ctr[4];  // 0: C sub-chunks loaded, 1: top sub-chunks loaded, 2: steps done, 3: stored
+struct alignas(8) Shared {
+  uint32_t ctr[6];  // 0: C sub-chunks loaded, 1: top units loaded, 2: steps done, 3: sub-chunks stored,
+                    // 4: units published, 5: unused
   uint32_t item;
   uint32_t abort;
 };
 
+// Both readiness counters of the compute wave in one 8-byte LDS read.
+__device__ __forceinline__ uint64_t load_ready(const Shared& sh) {
+  return __hip_atomic_load(reinterpret_cast<const uint64_t*>(&sh.ctr[0]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Every role below launders the kernel-wide sizes it uses through opaque() first:
+// otherwise the compiler hoists each role's per-row address arithmetic out of the band loop
+// and keeps all of it live across every role, which does not fit 256 registers per wave.
+
 // ---------------------------------------------------------------------------------------
-// wave 0: the cell chain
-template <typename T, int G>
-__device__ __forceinline__ void compute_band(T* S, const T* Tr, Shared& sh, Control* ctl, int band,
-                                             int Us, int Uc) {
-  using C = FwdCfg<T, G>;
-  using E = typename C::E;
+// wave 0: the cell chains
+template <typename T, int G, int R>
+struct ComputeState {
+  T X[R];   // previous value of each sub-band (W of the next cell)
+  T NW[R];  // previous N of each sub-band
+  T Q[R];   // for k >= 1: lane 63 of sub-band k-1 two steps back (rotated to lane 0)
+};
+
+template <typename T, int G, int R>
+struct UnitRegs {
+  Vec4<T> c[2][R];  // C of the unit's first two groups, per sub-band
+  Vec4<T> t[2];     // top values of the unit's first two groups
+};
+
+template <typename T, int G, int R>
+__device__ __forceinline__ void load_group(const T* __restrict__ S, const T* __restrict__ Tr, int slot, int lane,
+                                           Vec4<T> (&c)[R], Vec4<T>& t) {
+  using C = FwdCfg<T, G, R>;
+#pragma unroll
+  for (int k = 0; k < R; ++k) c[k] = *reinterpret_cast<const Vec4<T>*>(S + (k * kBand + lane) * C::PITCH + slot);
+  t = *reinterpret_cast<const Vec4<T>*>(Tr + slot);
+}
+
+template <typename T, int G, int R>
+__device__ __forceinline__ void cells4(ComputeState<T, G, R>& st, const Vec4<T> (&c)[R], const Vec4<T>& t,
+                                       Vec4<T> (&out)[R]) {
+  using E = Elem<T>;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T N[R], Qn[R];
+    N[0] = E::shr1(st.X[0], t.v[q]);  // lane 0 takes the row above the band
+#pragma unroll
+    for (int k = 1; k < R; ++k) {
+      N[k] = E::shr1(st.X[k], st.Q[k]);  // lane 0 takes lane 63 of sub-band k-1
+      Qn[k] = ror1(st.X[k - 1]);         // ... for the next step
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const T v = E::min3(st.NW[k], N[k], st.X[k]);
+      st.X[k] = E::add(c[k].v[q], v);
+      st.NW[k] = N[k];
+      out[k].v[q] = st.X[k];
+    }
+#pragma unroll
+    for (int k = 1; k < R; ++k) st.Q[k] = Qn[k];
+  }
+}
+
+// Waits until the C sub-chunk and the top unit that unit u reads are in LDS.
+template <typename T, int G, int R>
+__device__ __forceinline__ bool unit_ready(uint64_t ready, int u, Shared& sh, Control* ctl, uint32_t& stall_c,
+                                           uint32_t& stall_t, uint64_t& waited, bool trace) {
+  const uint32_t need_c = (uint32_t)((G * u) / kSub + 1);
+  const uint32_t need_t = (uint32_t)(u + 1);
+  const bool c_ok = (uint32_t)ready >= need_c, t_ok = (uint32_t)(ready >> 32) >= need_t;
+  if (trace) {
+    stall_c += !c_ok;
+    stall_t += !t_ok;
+  }
+  if (c_ok && t_ok) return true;
+  return lds_wait_ge(&sh.ctr[0], need_c, &sh.abort, ctl, waited) &&
+         lds_wait_ge(&sh.ctr[1], need_t, &sh.abort, ctl, waited);
+}
+
+// One unit of G steps.  'in' holds the first two groups of unit u (already read); the reads
+// of each later group are issued two groups ahead, and the last two groups issue the reads
+// of unit u+1 into 'out' (after checking that unit u+1 is ready).
+template <typename T, int G, int R>
+__device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restrict__ Tr, Shared& sh, Control* ctl,
+                                             int u, int Us, ComputeState<T, G, R>& st, const UnitRegs<T, G, R>& in,
+                                             UnitRegs<T, G, R>& out, uint32_t& stall_c, uint32_t& stall_t,
+                                             uint64_t& waited, bool trace) {
+  using C = FwdCfg<T, G, R>;
+  constexpr int NG = C::NG;
   const int lane = threadIdx.x & 63;
-  T D = E::inf();
-  T NW = (lane == 0 && band == 0) ? E::zero() : E::inf();  // virtual corner D[-1][-1] = 0
-  for (int u = 0; u < Us; ++u) {
-    const uint32_t need = (uint32_t)(u + 1 < Uc ? u + 1 : Uc);
-    if (!lds_wait_ge(&sh.ctr[0], need, &sh.abort, ctl) || !lds_wait_ge(&sh.ctr[1], need, &sh.abort, ctl)) {
-      sh.abort = 1u;
-      return;
-    }
-    // Steps past the last loaded column still write D in place into slots whose previous
-    // lap (sub-chunk u - RING/G) must have been stored first.  For u < Uc the loader has
-    // already waited for exactly that before publishing sub-chunk u.
-    const int lap = u - C::RING / G;
-    if (u >= Uc && lap >= 0 && !lds_wait_ge(&sh.ctr[3], (uint32_t)(lap + 1), &sh.abort, ctl)) {
-      sh.abort = 1u;
-      return;
-    }
-    const int base = (G * u) & C::MASK;
-    T* srow = S + lane * C::PITCH + base;
-    const T* trow = Tr + base;
+  const int base = (G * u) & C::MASK;
+  const int next_base = (G * (u + 1)) & C::MASK;
+  const bool has_next = u + 1 < Us;
+  const uint64_t ready = load_ready(sh);  // for unit u+1, used two groups before the end
+  __builtin_amdgcn_sched_barrier(0);
+  Vec4<T> cv[NG + 2][R], tv[NG + 2];
 #pragma unroll
-    for (int g = 0; g < G / 4; ++g) {
-      const Vec4<T> cv = *reinterpret_cast<const Vec4<T>*>(srow + 4 * g);
-      const Vec4<T> tv = *reinterpret_cast<const Vec4<T>*>(trow + 4 * g);
-      Vec4<T> out;
+  for (int p = 0; p < 2; ++p) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T N = E::shr1(D, tv.v[q]);   // lane 0 takes the row above the band
-        const T v = E::min3(NW, N, D);
-        D = E::add(cv.v[q], v);
-        NW = N;
-        out.v[q] = D;
+    for (int k = 0; k < R; ++k) cv[p][k] = in.c[p][k];
+    tv[p] = in.t[p];
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (g + 2 < NG) {
+      load_group<T, G, R>(S, Tr, base + 4 * (g + 2), lane, cv[g + 2], tv[g + 2]);
+    } else if (has_next) {
+      if (g + 2 == NG) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (!unit_ready<T, G, R>(ready, u + 1, sh, ctl, stall_c, stall_t, waited, trace)) return false;
+        __builtin_amdgcn_sched_barrier(0);
       }
-      *reinterpret_cast<Vec4<T>*>(srow + 4 * g) = out;
+      load_group<T, G, R>(S, Tr, next_base + 4 * (g + 2 - NG), lane, out.c[g + 2 - NG], out.t[g + 2 - NG]);
     }
-    lds_publish(&sh.ctr[2], (uint32_t)(G * (u + 1)));
-  }
-}
-
-// ---------------------------------------------------------------------------------------
-// wave 1: global -> LDS loader
-template <typename T, int G>
-__device__ __forceinline__ void load_sub(Vec4<T> (&buf)[G / 4], const FwdArgs& a, int64_t row0,
-                                         int u) {
-  using C = FwdCfg<T, G>;
-  using E = typename C::E;
-  const int lane = threadIdx.x & 63;
-  const T* Cp = static_cast<const T*>(a.C);
+    Vec4<T> d[R];
+    cells4<T, G, R>(st, cv[g], tv[g], d);
 #pragma unroll
-  for (int k = 0; k < C::VPL; ++k) {
-    const int idx = k * 64 + lane;
-    const int r = idx / C::VPR;
-    const int64_t col = (int64_t)G * u + 4 * (idx % C::VPR);
-    const int64_t row = row0 + r;
-    Vec4<T> v;
-    if (row < a.m && col + 3 < a.n) {
-      __builtin_memcpy(&v, Cp + row * a.ldc + col, sizeof(v));
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        v.v[e] = (row < a.m && col + e < a.n) ? Cp[row * a.ldc + col + e] : E::inf();
-    }
-    buf[k] = v;
+    for (int k = 0; k < R; ++k) *reinterpret_cast<Vec4<T>*>(S + (k * kBand + lane) * C::PITCH + base + 4 * g) = d[k];
   }
-}
-
-template <typename T, int G>
-__device__ __forceinline__ void store_sub_lds(T* S, const Vec4<T> (&buf)[G / 4], int u) {
-  using C = FwdCfg<T, G>;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int k = 0; k < C::VPL; ++k) {
-    const int idx = k * 64 + lane;
-    const int r = idx / C::VPR;
-    const int col = G * u + 4 * (idx % C::VPR);
-    T* srow = S + r * C::PITCH;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) srow[(r + col + e) & C::MASK] = buf[k].v[e];
-  }
-}
-
-template <typename T, int G>
-__device__ __forceinline__ bool loader_slot(T* S, const Vec4<T> (&buf)[G / 4], Shared& sh,
-                                            Control* ctl, int u) {
-  using C = FwdCfg<T, G>;
-  // Sub-chunk u reuses the slots of sub-chunk u - RING/G, which must be stored already.  On
-  // the first lap the slots that wrap around belong to negative columns (row r, slots
-  // < r), which the compute wave writes at steps < 64: it must have passed the last of
-  // them, step G*u + G - 1 + 63 - RING.
-  const int older = u - C::RING / G;
-  if (older >= 0) {
-    if (!lds_wait_ge(&sh.ctr[3], (uint32_t)(older + 1), &sh.abort, ctl)) return false;
-  } else {
-    const int steps = G * u + G + kBand - 1 - C::RING;
-    if (steps > 0 && !lds_wait_ge(&sh.ctr[2], (uint32_t)steps, &sh.abort, ctl)) return false;
-  }
-  store_sub_lds<T, G>(S, buf, u);
-  lds_publish(&sh.ctr[0], (uint32_t)(u + 1));
+  lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
+  __builtin_amdgcn_sched_barrier(0);
   return true;
 }
 
-template <typename T, int G>
-__device__ __forceinline__ void loader_band(T* S, Shared& sh, const FwdArgs& a, int band, int Uc) {
-  using C = FwdCfg<T, G>;
-  using E = typename C::E;
+template <typename T, int G, int R>
+__device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restrict__ Tr, Shared& sh, Control* ctl,
+                                             int band, int Us, uint64_t* trace) {
+  using E = Elem<T>;
   const int lane = threadIdx.x & 63;
-  const int64_t row0 = (int64_t)band * kBand;
-  // negative columns: row r reads slots 0 .. r-1 before its first real column
-  Vec4<T> inf4;
+  ComputeState<T, G, R> st;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) inf4.v[e] = E::inf();
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int idx = k * 64 + lane;
-    *reinterpret_cast<Vec4<T>*>(S + (idx >> 4) * C::PITCH + 4 * (idx & 15)) = inf4;
+  for (int k = 0; k < R; ++k) {
+    st.X[k] = E::inf();
+    st.NW[k] = E::inf();
+    st.Q[k] = E::inf();
   }
-  Vec4<T> buf[C::PF][C::VPL];
+  if (lane == 0 && band == 0) st.NW[0] = E::zero();  // virtual corner D[-1][-1] = 0
+  uint32_t stall_c = 0, stall_t = 0;
+  uint64_t t_first = 0, waited = 0;
+  const bool tr = trace != nullptr;
+  UnitRegs<T, G, R> P, Q;
+  if (!unit_ready<T, G, R>(load_ready(sh), 0, sh, ctl, stall_c, stall_t, waited, tr)) {
+    sh.abort = 1u;
+    return;
+  }
+  if (tr) t_first = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
-  for (int p = 0; p < C::PF; ++p)
-    if (p < Uc) load_sub<T, G>(buf[p], a, row0, p);
-  for (int u0 = 0; u0 < Uc; u0 += C::PF) {
-#pragma unroll
-    for (int p = 0; p < C::PF; ++p) {
-      const int u = u0 + p;
-      if (u < Uc) {
-        if (!loader_slot<T, G>(S, buf[p], sh, a.ctl, u)) {
-          sh.abort = 1u;
-          return;
-        }
-        if (u + C::PF < Uc) load_sub<T, G>(buf[p], a, row0, u + C::PF);
-      }
+  for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, Tr, 4 * p, lane, P.c[p], P.t[p]);
+  // Units in pairs, so the next unit's prefetched registers alternate between P and Q
+  // without copies.
+  int u = 0;
+  for (; u + 1 < Us; u += 2) {
+    if (!compute_unit<T, G, R>(S, Tr, sh, ctl, u, Us, st, P, Q, stall_c, stall_t, waited, tr) ||
+        !compute_unit<T, G, R>(S, Tr, sh, ctl, u + 1, Us, st, Q, P, stall_c, stall_t, waited, tr)) {
+      sh.abort = 1u;
+      return;
     }
+    if (tr && u == 62 / G) trace[16] = __builtin_amdgcn_s_memrealtime();
+  }
+  if (u < Us && !compute_unit<T, G, R>(S, Tr, sh, ctl, u, Us, st, P, Q, stall_c, stall_t, waited, tr)) {
+    sh.abort = 1u;
+    return;
+  }
+  if (tr && lane == 0) {
+    trace[1] = t_first;
+    trace[2] = __builtin_amdgcn_s_memrealtime();
+    trace[4] = stall_c;
+    trace[5] = stall_t;
+    trace[8] = waited;
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// wave 2: top boundary poller
-template <typename T, int G>
-__device__ __forceinline__ void top_band(T* Tr, Shared& sh, const FwdArgs& a, int band, int Uc,
-                                         uint32_t epoch) {
-  using C = FwdCfg<T, G>;
+// wave 1: global -> LDS loader.
+//
+// Vector k of a lane covers row i = 4k + lane/16 and slots [64s + 4j, 64s + 4j + 4) of
+// sub-chunk s, j = lane % 16, i.e. columns c0 .. c0+3 with c0 = 64s + 4j - skew(i).
+template <typename T, int G, int R>
+__device__ __forceinline__ void load_sub(Vec4<T> (&buf)[16 * R], __amdgpu_buffer_rsrc_t rsrc, int64_t ldc, int s) {
+  using C = FwdCfg<T, G, R>;
+  const int lane = threadIdx.x & 63;
+  // Loads of different sub-chunks stay in issue order, so the wait before a sub-chunk's
+  // LDS write leaves the later sub-chunks in flight.  Columns outside [0, n) read
+  // neighbouring row data; an offset below the band's start (possible only for a single
+  // column, where i*ldc + c0 can reach -1) wraps to a huge unsigned value and, like reads
+  // past the band's end, returns zeros from the range-checked buffer; store_sub_lds masks
+  // all of them.
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 16 * R; ++k) {
+    const int i = 4 * k + (lane >> 4);
+    const int c0 = kSub * s + 4 * (lane & 15) - C::skew(i);
+    const uint32_t off = (uint32_t)((int64_t)i * ldc + c0) * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 4) {
+      buf[k] = __builtin_bit_cast(Vec4<T>, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
+    } else {
+      struct Hf { T x[2]; };
+      const Hf lo = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
+      const Hf hi = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(off + 16), 0, 0));
+      buf[k].v[0] = lo.x[0]; buf[k].v[1] = lo.x[1]; buf[k].v[2] = hi.x[0]; buf[k].v[3] = hi.x[1];
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// A sub-chunk with every row real and every column in [0, n) needs no masking.
+template <typename T, int G, int R>
+__device__ __forceinline__ bool interior_sub(int s, int rows, int64_t n) {
+  using C = FwdCfg<T, G, R>;
+  return rows == C::H && kSub * s >= C::skew(C::H - 1) && (int64_t)kSub * s + kSub <= n;
+}
+
+template <typename T, int G, int R>
+__device__ __forceinline__ void store_sub_lds(T* S, const Vec4<T> (&buf)[16 * R], int s, int rows, int64_t n) {
+  using C = FwdCfg<T, G, R>;
+  using E = typename C::E;
+  const int lane = threadIdx.x & 63;
+  const bool interior = interior_sub<T, G, R>(s, rows, n);
+#pragma unroll
+  for (int k = 0; k < 16 * R; ++k) {
+    const int i = 4 * k + (lane >> 4);
+    const int slot = (kSub * s + 4 * (lane & 15)) & C::MASK;
+    Vec4<T> v = buf[k];
+    if (!interior) {
+      const int64_t c0 = (int64_t)kSub * s + 4 * (lane & 15) - C::skew(i);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i >= rows || c0 + e < 0 || c0 + e >= n) v.v[e] = E::inf();
+    }
+    *reinterpret_cast<Vec4<T>*>(S + i * C::PITCH + slot) = v;
+  }
+}
+
+template <typename T, int G, int R>
+__device__ __forceinline__ void loader_band(T* S, Shared& sh, const FwdArgs& a, int band, int Ks, uint64_t* tr) {
+  using C = FwdCfg<T, G, R>;
+  const int64_t ldc = opaque(a.ldc), n = opaque(a.n);
+  const int64_t row0 = (int64_t)band * C::H;
+  const int rows = (int)(a.m - row0 < C::H ? a.m - row0 : C::H);
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(static_cast<const T*>(a.C) + row0 * ldc,
+                                                (uint32_t)(((rows - 1) * ldc + n) * (int64_t)sizeof(T)));
+  uint64_t waited = 0;
+  Vec4<T> buf[C::PF][16 * R];
+#pragma unroll
+  for (int p = 0; p < C::PF; ++p) load_sub<T, G, R>(buf[p], rsrc, ldc, p);
+  for (int s0 = 0; s0 < Ks; s0 += C::PF) {
+#pragma unroll
+    for (int p = 0; p < C::PF; ++p) {
+      const int s = s0 + p;
+      if (s < Ks) {
+        // sub-chunk s reuses the slots of sub-chunk s - RING/64, which must be stored (by
+        // the storer) and whose last rows must be read (by the publisher)
+        const int older = s - C::RING / kSub;
+        if (older >= 0 && (!lds_wait_ge<false>(&sh.ctr[3], (uint32_t)(older + 1), &sh.abort, a.ctl, waited) ||
+                           !lds_wait_ge<false>(&sh.ctr[4], (uint32_t)(C::GPS * (older + 1)), &sh.abort, a.ctl,
+                                               waited))) {
+          sh.abort = 1u;
+          return;
+        }
+        store_sub_lds<T, G, R>(S, buf[p], s, rows, n);
+        lds_signal(&sh.ctr[0], (uint32_t)(s + 1));
+        if (s + C::PF < Ks) load_sub<T, G, R>(buf[p], rsrc, ldc, s + C::PF);
+      }
+    }
+  }
+  if (tr && (threadIdx.x & 63) == 0) {
+    tr[9] = waited;
+    tr[12] = __builtin_amdgcn_s_memrealtime();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// wave 2: top boundary poller, G columns per unit
+template <typename T, int G, int R>
+__device__ __forceinline__ void top_band(T* Tr, Shared& sh, const FwdArgs& a, int band, int Ut, uint32_t epoch,
+                                         uint64_t* tr) {
+  using C = FwdCfg<T, G, R>;
   using E = typename C::E;
   constexpr int W = E::W;
   const int lane = threadIdx.x & 63;
-  const int64_t n = a.n;
-  for (int u = 0; u < Uc; ++u) {
-    // the top ring slot of column j is reused RING steps later
+  const int64_t n = opaque(a.n);
+  uint64_t waited = 0;
+  for (int u = 0; u < Ut; ++u) {
+    // the top ring slot of column j is read at step j and reused RING steps later
     const int64_t need_steps = (int64_t)G * u + G - C::RING;
-    if (need_steps > 0 && !lds_wait_ge(&sh.ctr[2], (uint32_t)need_steps, &sh.abort, a.ctl)) {
+    if (need_steps > 0 && !lds_wait_ge(&sh.ctr[2], (uint32_t)need_steps, &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return;
     }
@@ -246,6 +416,7 @@ __device__ __forceinline__ void top_band(T* Tr, Shared& sh, const FwdArgs& a, in
             if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) { raise_timeout(a.ctl); give_up = true; break; }
           }
         }
+        waited += __builtin_amdgcn_s_memrealtime() - t0;
         if (give_up) {
           sh.abort = 1u;
           return;
@@ -254,85 +425,167 @@ __device__ __forceinline__ void top_band(T* Tr, Shared& sh, const FwdArgs& a, in
       if (mine) val = E::from_words(w);
     }
     if (lane < G) Tr[(G * u + lane) & C::MASK] = val;
-    lds_publish(&sh.ctr[1], (uint32_t)(u + 1));
+    lds_signal(&sh.ctr[1], (uint32_t)(u + 1));
+    if (tr && u == 0 && lane == 0) tr[15] = __builtin_amdgcn_s_memrealtime();
+  }
+  if (tr && lane == 0) {
+    tr[10] = waited;
+    tr[13] = __builtin_amdgcn_s_memrealtime();
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// wave 3: storer / publisher
-template <typename T, int G>
-__device__ __forceinline__ void store_band(const T* S, Shared& sh, const FwdArgs& a, int band, int Uc,
-                                           uint32_t epoch) {
-  using C = FwdCfg<T, G>;
-  using E = typename C::E;
-  constexpr int W = E::W;
+// wave 3: storer
+template <typename T, int G, int R>
+__device__ __forceinline__ void store_sub(const T* S, __amdgpu_buffer_rsrc_t drs, int64_t ldd, int64_t n, int rows,
+                                          int s) {
+  using C = FwdCfg<T, G, R>;
+  typedef int v4i __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
-  const int64_t m = a.m, n = a.n;
-  const int64_t row0 = (int64_t)band * kBand;
-  const bool last_band = band == a.nb - 1;
-  T* Dp = static_cast<T*>(a.D);
-  T* ck_rows = static_cast<T*>(a.ckpt);
-  T* ck_cols = ck_rows ? ck_rows + (int64_t)(a.nb - 1) * n : nullptr;
-  const int K = a.ckpt_k;
-  for (int v = 0; v < Uc; ++v) {
-    const int64_t j0 = (int64_t)G * v;
-    const int64_t jend = j0 + G < n ? j0 + G : n;
-    if (!lds_wait_ge(&sh.ctr[2], (uint32_t)(jend + kBand - 1), &sh.abort, a.ctl)) {
-      sh.abort = 1u;
-      return;
-    }
-    // 1. the band's last row, latency critical: it unblocks the band below
-    if (!last_band && lane < G && j0 + lane < n) {
-      const int64_t j = j0 + lane;
-      const T x = S[(kBand - 1) * C::PITCH + ((kBand - 1 + (int)j) & C::MASK)];
+  const int j4 = 4 * (lane & 15);
+  const int slot = (kSub * s + j4) & C::MASK;
+  if (interior_sub<T, G, R>(s, rows, n)) {
+    // Interior sub-chunk: 16 LDS reads first, then one 16-byte store per 16 bytes.
 #pragma unroll
-      for (int k = 0; k < W; ++k) store_word(a.bnd + ((int64_t)band * n + j) * W + k, tagged(E::word(x, k), epoch));
-      if (ck_rows) ck_rows[(int64_t)band * n + j] = x;
-    }
-    // 2. the table, coalesced
-    if (Dp) {
+    for (int h = 0; h < R; ++h) {
+      Vec4<T> v[16];
 #pragma unroll
-      for (int k = 0; k < C::VPL; ++k) {
-        const int idx = k * 64 + lane;
-        const int r = idx / C::VPR;
-        const int64_t col = j0 + 4 * (idx % C::VPR);
-        const int64_t row = row0 + r;
-        if (row < m && col < n) {
-          const T* srow = S + r * C::PITCH;
-          Vec4<T> x;
+      for (int k = 0; k < 16; ++k) {
+        const int i = 64 * h + 4 * k + (lane >> 4);
+        v[k] = *reinterpret_cast<const Vec4<T>*>(S + i * C::PITCH + slot);
+      }
 #pragma unroll
-          for (int e = 0; e < 4; ++e) x.v[e] = srow[(r + (int)col + e) & C::MASK];
-          T* dst = Dp + row * a.ldd + col;
-          if (col + 3 < n) {
-            __builtin_memcpy(dst, &x, sizeof(x));
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (col + e < n) dst[e] = x.v[e];
-          }
+      for (int k = 0; k < 16; ++k) {
+        const int i = 64 * h + 4 * k + (lane >> 4);
+        const int off = (int)(((int64_t)i * ldd + kSub * s + j4 - C::skew(i)) * (int64_t)sizeof(T));
+        if constexpr (sizeof(T) == 4) {
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v[k]), drs, off, 0, 0);
+        } else {
+          struct Hf { v4i lo, hi; };
+          const Hf hh = __builtin_bit_cast(Hf, v[k]);
+          __builtin_amdgcn_raw_buffer_store_b128(hh.lo, drs, off, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(hh.hi, drs, off + 16, 0, 0);
         }
       }
     }
-    // 3. checkpoint columns: D[.][Kq-1] for 1 <= q < ceil(n/K)
-    if (ck_cols) {
-      const int64_t row = row0 + lane;
-      for (int64_t j = ((j0 + K) / K) * K - 1; j < jend; j += K) {
-        if (j + 1 < n && row < m)
-          ck_cols[((j + 1) / K - 1) * m + row] = S[lane * C::PITCH + ((lane + (int)j) & C::MASK)];
+    return;
+  }
+  // Edge sub-chunk (first, last, or a partial band): element-wise, only inside the matrix.
+  for (int k = 0; k < 16 * R; ++k) {
+    const int i = 4 * k + (lane >> 4);
+    const int64_t c0 = (int64_t)kSub * s + j4 - C::skew(i);
+    if (i >= rows) continue;
+    const Vec4<T> v = *reinterpret_cast<const Vec4<T>*>(S + i * C::PITCH + slot);
+    const int off = (int)(((int64_t)i * ldd + c0) * (int64_t)sizeof(T));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (c0 + e >= 0 && c0 + e < n) {
+        if constexpr (sizeof(T) == 4) {
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v.v[e]), drs, off + 4 * e, 0, 0);
+        } else {
+          typedef int v2i __attribute__((ext_vector_type(2)));
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v.v[e]), drs, off + 8 * e, 0, 0);
+        }
       }
     }
-    // 4. the score
-    if (last_band && v == Uc - 1 && lane == (int)(m - 1 - row0))
-      *static_cast<T*>(a.score) = S[lane * C::PITCH + ((lane + (int)(n - 1)) & C::MASK)];
-    lds_publish(&sh.ctr[3], (uint32_t)(v + 1));
   }
 }
 
+template <typename T, int G, int R>
+__device__ __forceinline__ void store_band(const T* S, Shared& sh, const FwdArgs& a, int band, int Ks,
+                                           uint64_t* tr) {
+  using C = FwdCfg<T, G, R>;
+  const int lane = threadIdx.x & 63;
+  const int64_t m = opaque(a.m), n = opaque(a.n), ldd = opaque(a.ldd);
+  const int64_t row0 = (int64_t)band * C::H;
+  const int rows = (int)(m - row0 < C::H ? m - row0 : C::H);
+  T* ck_cols = a.ckpt ? static_cast<T*>(a.ckpt) + ((m + kBand - 1) / kBand - 1) * n : nullptr;
+  const int K = a.ckpt_k;
+  const int64_t sc_row = m - 1 - row0;  // band row of the score, if it lies in this band
+  const __amdgpu_buffer_rsrc_t drs =
+      make_rsrc(a.D ? static_cast<T*>(a.D) + row0 * ldd : nullptr,
+                a.D ? (uint32_t)(((rows - 1) * ldd + n) * (int64_t)sizeof(T)) : 0u);
+  uint64_t waited = 0;
+  for (int s = 0; s < Ks; ++s) {
+    // sub-chunk s (slots [64s, 64s+64) of every row) is final after step 64s + 63
+    if (!lds_wait_ge(&sh.ctr[2], (uint32_t)(kSub * (s + 1)), &sh.abort, a.ctl, waited)) {
+      sh.abort = 1u;
+      return;
+    }
+    if (a.D) store_sub<T, G, R>(S, drs, ldd, n, rows, s);
+    if (ck_cols) {
+#pragma unroll
+      for (int h = 0; h < R; ++h) {
+        const int i = 64 * h + lane;
+        if (i >= rows) continue;
+        // checkpoint columns D[.][Kq-1] of row i held by sub-chunk s
+        const int64_t lo = (int64_t)kSub * s - C::skew(i), hi = lo + kSub;
+        for (int64_t j = ((lo > 0 ? lo : 0) + K) / K * K - 1; j < hi; j += K) {
+          if (j >= lo && j + 1 < n)
+            ck_cols[((j + 1) / K - 1) * m + row0 + i] = S[i * C::PITCH + ((int)(j + C::skew(i)) & C::MASK)];
+        }
+      }
+    }
+    if (sc_row >= 0 && sc_row < C::H && lane == (int)(sc_row % kBand)) {
+      const int64_t slot = n - 1 + C::skew((int)sc_row);
+      if (slot / kSub == s) *static_cast<T*>(a.score) = S[sc_row * C::PITCH + ((int)slot & C::MASK)];
+    }
+    lds_publish(&sh.ctr[3], (uint32_t)(s + 1));
+  }
+  if (tr && lane == 0) tr[11] = waited;
+}
+
 // ---------------------------------------------------------------------------------------
-template <typename T, int G>
+// wave 4: publisher of the band's last row (and of the checkpoint rows)
+template <typename T, int G, int R>
+__device__ __forceinline__ void publish_band(const T* S, Shared& sh, const FwdArgs& a, int band, int Us,
+                                             uint32_t epoch, uint64_t* tr) {
+  using C = FwdCfg<T, G, R>;
+  using E = typename C::E;
+  constexpr int W = E::W;
+  const int lane = threadIdx.x & 63;
+  const int64_t m = opaque(a.m), n = opaque(a.n);
+  const int nb64 = (int)((m + kBand - 1) / kBand);  // 64-row bands of the checkpoint grid
+  const bool last_band = band == a.nb - 1;
+  T* ck_rows = static_cast<T*>(a.ckpt);
+  uint64_t waited = 0;
+  for (int u = 0; u < Us; ++u) {
+    if (!lds_wait_ge(&sh.ctr[2], (uint32_t)(G * (u + 1)), &sh.abort, a.ctl, waited)) {
+      sh.abort = 1u;
+      return;
+    }
+    if (tr && u == 62 / G + 1 && lane == 0) tr[17] = __builtin_amdgcn_s_memrealtime();
+    if (lane < G) {
+      const int slot = (G * u + lane) & C::MASK;
+      // the band's last row, row H-1, finished column Gu + lane - skew(H-1) at this step
+      const int64_t j = (int64_t)G * u + lane - C::skew(C::H - 1);
+      if (!last_band && j >= 0 && j < n) {
+        const T x = S[(C::H - 1) * C::PITCH + slot];
+#pragma unroll
+        for (int k = 0; k < W; ++k) store_word(a.bnd + ((int64_t)band * n + j) * W + k, tagged(E::word(x, k), epoch));
+      }
+      // checkpoint rows: the last row of every 64-row sub-band except the matrix's last one
+      if (ck_rows) {
+#pragma unroll
+        for (int h = 0; h < R; ++h) {
+          const int i = 64 * h + 63;
+          const int b64 = band * R + h;
+          const int64_t jc = (int64_t)G * u + lane - C::skew(i);
+          if (b64 < nb64 - 1 && jc >= 0 && jc < n) ck_rows[(int64_t)b64 * n + jc] = S[i * C::PITCH + slot];
+        }
+      }
+    }
+    if (tr && u == 62 / G + 1 && lane == 0) tr[14] = __builtin_amdgcn_s_memrealtime();
+    lds_publish(&sh.ctr[4], (uint32_t)(u + 1));
+  }
+  if (tr && lane == 0) tr[18] = waited;
+}
+
+// ---------------------------------------------------------------------------------------
+template <typename T, int G, int R>
 __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
-  using C = FwdCfg<T, G>;
-  __shared__ Vec4<T> S4[kBand * C::PITCH / 4];
+  using C = FwdCfg<T, G, R>;
+  __shared__ Vec4<T> S4[C::H * C::PITCH / 4];
   __shared__ Vec4<T> Tr4[C::RING / 4];
   __shared__ Shared sh;
   T* S = reinterpret_cast<T*>(S4);
@@ -340,45 +593,72 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
   const int wave = threadIdx.x >> 6;
   Control* ctl = a.ctl;
   const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int Uc = (int)((a.n + G - 1) / G);
-  const int Us = (int)((a.n + kBand - 1 + G - 1) / G);
+  // steps of a band: n + skew(H-1), rounded up to whole 64-slot sub-chunks
+  const int Ks = (int)((a.n + C::skew(C::H - 1) + kSub - 1) / kSub);  // C sub-chunks
+  const int Us = Ks * C::GPS;                                          // compute / publish units
+  const int Ut = (int)((a.n + G - 1) / G);                             // top units holding real columns
   if (threadIdx.x == 0) sh.abort = 0u;
   for (;;) {
-    if (threadIdx.x < 4) sh.ctr[threadIdx.x] = 0u;
+    if (threadIdx.x < 6) sh.ctr[threadIdx.x] = 0u;
     claim_next(ctl, &sh.item, &sh.abort);
     const int band = (int)sh.item;
     if (band >= a.nb || sh.abort != 0u) break;
-    if (wave == 0)
-      compute_band<T, G>(S, Tr, sh, ctl, band, Us, Uc);
-    else if (wave == 1)
-      loader_band<T, G>(S, sh, a, band, Uc);
-    else if (wave == 2)
-      top_band<T, G>(Tr, sh, a, band, Uc, epoch);
-    else
-      store_band<T, G>(S, sh, a, band, Uc, epoch);
+    uint64_t* tr = a.trace ? a.trace + (int64_t)band * kTraceWords : nullptr;
+    if (tr && threadIdx.x == 0) {
+      unsigned xcc;
+      asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+      tr[0] = __builtin_amdgcn_s_memrealtime();
+      tr[6] = xcc;
+      tr[7] = blockIdx.x;
+    }
+    if (wave == 0) {
+      compute_band<T, G, R>(S, Tr, sh, ctl, band, Us, tr);
+    } else if (wave == 1) {
+      loader_band<T, G, R>(S, sh, a, band, Ks, tr);
+    } else if (wave == 2) {
+      top_band<T, G, R>(Tr, sh, a, band, Ut, epoch, tr);
+      // Top units beyond the last real column hold no values any real cell reads; mark
+      // them loaded so that the compute wave's readiness test stays one comparison.
+      if ((threadIdx.x & 63) == 0 && sh.abort == 0u) lds_signal(&sh.ctr[1], 0x7fffffffu);
+    } else if (wave == 3) {
+      store_band<T, G, R>(S, sh, a, band, Ks, tr);
+    } else {
+      publish_band<T, G, R>(S, sh, a, band, Us, epoch, tr);
+    }
+    if (tr && threadIdx.x == 3 * 64) tr[3] = __builtin_amdgcn_s_memrealtime();
     __syncthreads();
   }
   finish_launch(ctl, epoch);
 }
 
-template <typename T>
+template <typename T, int R>
 hipError_t launch_t(int tile, const FwdArgs& a, int grid, hipStream_t s) {
   switch (tile) {
-    case 16: hipLaunchKernelGGL((fwd_kernel<T, 16>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((fwd_kernel<T, 32>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 64: hipLaunchKernelGGL((fwd_kernel<T, 64>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((fwd_kernel<T, 16, R>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((fwd_kernel<T, 32, R>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((fwd_kernel<T, 64, R>), dim3(grid), dim3(kThreads), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// 64-row sub-bands per band for the 4-byte types.  One is the fastest at 16384 x 16384 on
+// MI355X (R = 2 halves the handoffs but doubles the per-step work of the compute wave and
+// leaves half of the compute units idle at 256 bands); double always uses one.
+#ifndef WF_FWD_ROWS
+#define WF_FWD_ROWS 1
+#endif
+constexpr int kRowsF = WF_FWD_ROWS;
+
 }  // namespace
+
+int forward_band_rows(int dtype) { return dtype == 1 ? kBand : kBand * kRowsF; }
 
 hipError_t launch_forward(int dtype, int tile, const FwdArgs& a, int grid, hipStream_t s) {
   switch (dtype) {
-    case 0: return launch_t<float>(tile, a, grid, s);
-    case 1: return launch_t<double>(tile, a, grid, s);
-    case 2: return launch_t<int32_t>(tile, a, grid, s);
+    case 0: return launch_t<float, kRowsF>(tile, a, grid, s);
+    case 1: return launch_t<double, 1>(tile, a, grid, s);
+    case 2: return launch_t<int32_t, kRowsF>(tile, a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -10,8 +10,8 @@ namespace wf {
 // Rows per band: one band is swept by one 64-lane wavefront, lane r owning band row r.
 constexpr int kBand = 64;
 // Waves of a sweep workgroup: 0 = compute, 1 = input loader, 2 = top-boundary poller,
-// 3 = output storer / boundary publisher.
-constexpr int kWaves = 4;
+// 3 = output storer, 4 = boundary publisher.
+constexpr int kWaves = 5;
 constexpr int kThreads = kWaves * 64;
 
 // Device-resident control block of a workspace.  It resets itself: the last workgroup of a
@@ -36,12 +36,65 @@ struct FwdArgs {
   int64_t ldc, ldd;
   int64_t m, n;
   int32_t ckpt_k;   // 0 = no checkpoints
-  int32_t nb;       // bands = ceil(m / 64)
+  int32_t nb;       // bands of the sweep = ceil(m / forward_band_rows(dtype))
   Control* ctl;
-  uint64_t* bnd;    // (nb-1) * n * words-per-element handoff words
+  uint64_t* bnd;    // (nb-1) * n * words-per-element handoff words (last row of each band)
+  uint64_t* trace;  // null, or kTraceWords words per band (see wf_trace_enable)
+};
+
+// Per-band trace record, written when tracing is enabled (times in ticks of the 100 MHz
+// real-time counter):
+//   0 claim time        1 first sub-chunk ready   2 compute done     3 store done
+//   4 sub-chunks the compute wave found not yet loaded
+//   5 sub-chunks whose top row had not yet arrived
+//   6 XCC id            7 workgroup id
+//   8..11 ticks spent waiting by the compute, loader, top and storer waves
+//   12 loader done      13 top done               18 ticks the publisher waited
+//   14 time the storer published unit U1 = 62/G + 1, the one unit 0 of the band below needs
+//   15 time the poller completed unit 0
+//   16 time the compute wave finished unit U1
+//   17 time the publisher saw unit U1 finished
+//   19..23 reserved
+constexpr int kTraceWords = 24;
+
+// Arguments of the selection recompute (first half of the adjoint): every 64-row band is
+// swept again from its top row -- a checkpoint row, or a row of the saved table -- and
+// emits the 2-bit predecessor code of each cell (0 none / outside, 1 NW, 2 N, 3 W), packed
+// 16 per 32-bit word: word q of lane r of band b holds slots 16q .. 16q+15 of row 64b + r
+// (slot = row-in-band + column), at sel[(b * Q + q) * 64 + r], Q = ceil((n + 63) / 16).
+struct SelArgs {
+  const void* C;
+  const void* top;    // row 64b-1 of band b >= 1 is at top + (b-1) * ld_top
+  int64_t ldc, ld_top;
+  int64_t m, n;
+  int32_t nb;         // 64-row bands
+  int32_t Q;          // sel words per lane per band
+  uint32_t* sel;
+  Control* ctl;
+};
+
+// Arguments of the reverse adjoint sweep (second half): bands of 64 rows from the bottom
+// up, each from right to left, reading the selection codes and the upstream gradient.
+struct AdjArgs {
+  const uint32_t* sel;
+  const void* gD;       // may be null (zero)
+  const void* gscore;   // may be null (zero)
+  void* gC;
+  int64_t ldgd, ldgc;
+  int64_t m, n;
+  int32_t nb;           // 64-row bands
+  int32_t Q;
+  Control* ctl;
+  uint64_t* bnd;        // (nb-1) * n * 2 * words-per-element handoff words
+  uint64_t* trace;
 };
 
 // Host-side launchers (defined in wf_fwd.hip).  'tile' is 16, 32 or 64.
 hipError_t launch_forward(int dtype, int tile, const FwdArgs& a, int grid, hipStream_t s);
+// Rows per band of the forward sweep for a dtype (128 for 4-byte elements, 64 for double).
+int forward_band_rows(int dtype);
+// Adjoint launchers (defined in wf_bwd.hip), float (dtype 0) and double (dtype 1) only.
+hipError_t launch_select(int dtype, const SelArgs& a, int grid, hipStream_t s);
+hipError_t launch_adjoint(int dtype, int tile, const AdjArgs& a, int grid, hipStream_t s);
 
 }  // namespace wf

@@ -53,7 +53,7 @@ BAD_FORWARD = {
     "null C": dict(C=None),
     "null score": dict(score=None),
     "ckpt without k": dict(ckpt=0x1000, ckpt_k=0),
-    "k without ckpt": dict(ckpt=None, ckpt_k=64),
+    "k without ckpt": dict(m=100, ckpt=None, ckpt_k=64),
     "k too large": dict(ckpt=0x1000, ckpt_k=5000),
     "m*n overflow": dict(m=1 << 40, n=1 << 31, ldc=1 << 31, ldd=1 << 31),
 }
@@ -67,3 +67,34 @@ def test_forward_rejects_bad_arguments_before_device_work(lib, case):
     rc = lib.wf_forward(args["dtype"], args["m"], args["n"], args["C"], args["ldc"], args["D"], args["ldd"],
                         args["score"], args["ckpt"], args["ckpt_k"], args["stream"])
     assert rc == _lib.WF_E_ARG, case
+
+
+BAD_BACKWARD = {
+    "bad dtype": dict(dtype=7),
+    "int32 unsupported": dict(dtype=2, expect=_lib.WF_E_UNSUPPORTED),
+    "m = 0": dict(m=0),
+    "n = 0": dict(n=0),
+    "ldc < n": dict(ldc=3),
+    "ldgc < n": dict(ldgc=3),
+    "ldgd < n": dict(ldgd=3),
+    "ldd < n": dict(ldd=3),
+    "null C": dict(C=None),
+    "null g_C": dict(g_C=None),
+    "neither D nor ckpt": dict(D=None),
+    "both D and ckpt": dict(ckpt=0x5000, ckpt_k=64),
+    "ckpt without k": dict(D=None, ckpt=0x5000, ckpt_k=0),
+    "k without ckpt": dict(m=100, D=None, ckpt=None, ckpt_k=64),
+    "k too large": dict(D=None, ckpt=0x5000, ckpt_k=5000),
+    "m*n overflow": dict(m=1 << 40, n=1 << 31, ldc=1 << 31, ldd=1 << 31, ldgd=1 << 31, ldgc=1 << 31),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BAD_BACKWARD))
+def test_backward_rejects_bad_arguments_before_device_work(lib, case):
+    args = dict(dtype=0, m=8, n=8, C=0x1000, ldc=8, ckpt=None, ckpt_k=0, D=0x2000, ldd=8, g_score=0x3000,
+                g_D=0x4000, ldgd=8, g_C=0x6000, ldgc=8, stream=None, expect=_lib.WF_E_ARG)
+    args.update(BAD_BACKWARD[case])
+    rc = lib.wf_backward(args["dtype"], args["m"], args["n"], args["C"], args["ldc"], args["ckpt"], args["ckpt_k"],
+                         args["D"], args["ldd"], args["g_score"], args["g_D"], args["ldgd"], args["g_C"],
+                         args["ldgc"], args["stream"])
+    assert rc == args["expect"], case
