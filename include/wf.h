@@ -104,6 +104,50 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
                 int64_t ldgd, void* g_C, int64_t ldgc, void* stream);
 
 /*
+ * Ragged batch.  A plan describes a batch of independent instances of different sizes
+ * (instance i: m[i] x n[i], row-major with leading dimension n[i], at element offset
+ * offsets[i] of one buffer) and owns a device work list of (instance, band) items.
+ * wf_batch_forward sweeps every instance with ONE persistent launch; the launch is
+ * captured in a hipGraph the first time it is called with a given (C, D, scores) and the
+ * graph is replayed on later calls with the same pointers (other pointers re-capture,
+ * which synchronizes the device once).  Inside a stream capture of the caller's own the
+ * launch is recorded into the caller's graph instead.
+ *
+ * wf_plan_create(plan, dtype, batch, m, n, offsets, tile, rows, stream)
+ *   m, n       HOST arrays of 'batch' sizes (each >= 1).
+ *   offsets    HOST array of element offsets (instances must not overlap), or NULL to pack
+ *              the instances in order with 256-byte aligned starts (wf_plan_offsets
+ *              returns them).
+ *   tile       columns per handoff unit, 16/32/64, or 0 to autotune.
+ *   rows       64-row tiles held by one workgroup at a time (rows per band / 64): 1, 2
+ *              (not for WF_F64), or 0 to autotune.
+ *   stream     used by the autotuner.  Autotuning times every allowed (tile, rows) on
+ *              scratch buffers of the batch's size (allocated and freed inside the call,
+ *              which synchronizes 'stream'); results are cached per process and, if the
+ *              environment variable WF_TUNE_CACHE names a file, in that file.
+ *   Creates the plan (host and device memory owned by the library until
+ *   wf_plan_destroy).  Returns WF_E_ARG for invalid sizes or overlapping offsets.
+ * wf_plan_elems    number of elements the C (and D) buffer must hold, -1 for NULL.
+ * wf_plan_offsets  copies the batch's element offsets into a host array of 'batch'.
+ * wf_plan_config   the (tile, rows) the plan uses.
+ * wf_batch_forward(plan, C, D, scores, stream)
+ *   C       [in]  device buffer of wf_plan_elems elements holding every instance.
+ *   D       [out] same layout as C, every instance's table; NULL = scores only.
+ *   scores  [out] 'batch' elements, D_i[m_i-1][n_i-1].
+ *   The plan's device of creation must be current.  Calls on one plan must be ordered; a
+ *   plan shares the device workspace's control block with the other entry points.
+ * wf_plan_destroy  synchronizes the device and frees the plan (NULL is ignored).
+ */
+typedef struct wf_plan wf_plan;
+int wf_plan_create(wf_plan** plan, int dtype, int32_t batch, const int64_t* m, const int64_t* n,
+                   const int64_t* offsets, int32_t tile, int32_t rows, void* stream);
+int64_t wf_plan_elems(const wf_plan* plan);
+int wf_plan_offsets(const wf_plan* plan, int64_t* offsets);
+int wf_plan_config(const wf_plan* plan, int32_t* tile, int32_t* rows);
+int wf_batch_forward(wf_plan* plan, const void* C, void* D, void* scores, void* stream);
+void wf_plan_destroy(wf_plan* plan);
+
+/*
  * Force the tile width (columns per handoff unit, 64 rows per band) used by later calls on
  * this process: 16, 32 or 64, or 0 to return to the automatic choice.  Returns WF_E_ARG for
  * any other value.  Used by the autotuner and the tests.

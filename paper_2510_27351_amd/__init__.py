@@ -10,13 +10,15 @@ Reading R0 of the cell recurrence (the paper does not state one):
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import _lib
 from ._lib import WfError  # noqa: F401
 
-__all__ = ["forward", "backward", "sweep", "WfFunction", "ckpt_elems", "set_tile", "last_async_error",
-           "WfError", "BAND"]
+__all__ = ["forward", "backward", "sweep", "WfFunction", "Plan", "ckpt_elems", "set_tile",
+           "last_async_error", "WfError", "BAND"]
 
 BAND = 64  # rows per band of the device sweep (= wavefront size)
 
@@ -147,6 +149,76 @@ class WfFunction(torch.autograd.Function):
 def sweep(C: torch.Tensor, table: bool = False):
     """Autograd entry point: score (table=False) or (D, score) (table=True)."""
     return WfFunction.apply(C, table)
+
+
+class Plan:
+    """A ragged batch of independent instances swept by one persistent launch.
+
+    ms, ns: instance sizes; offsets: element offsets in one packed buffer (None = packed in
+    order with 256-byte aligned starts); tile / rows: 16/32/64 and 1/2, or 0 to autotune.
+    forward(C) takes the packed device buffer and returns (scores, D) -- D is None unless
+    table=True or a D buffer is given."""
+
+    def __init__(self, ms, ns, dtype=torch.float32, offsets=None, tile: int = 0, rows: int = 0, device=None):
+        if len(ms) != len(ns) or not len(ms):
+            raise ValueError("ms and ns must be non-empty and of equal length")
+        self.dtype = dtype
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.batch = len(ms)
+        self.ms, self.ns = [int(x) for x in ms], [int(x) for x in ns]
+        lib = _lib.load()
+        arr = ctypes.c_int64 * self.batch
+        m_arr, n_arr = arr(*self.ms), arr(*self.ns)
+        o_arr = arr(*[int(x) for x in offsets]) if offsets is not None else None
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib.wf_plan_create(ctypes.byref(self._h), _DTYPES[dtype] if dtype in _DTYPES else -1, self.batch,
+                                    m_arr, n_arr, o_arr, tile, rows, _stream(self.device))
+        _lib.check(rc, "wf_plan_create")
+        self.elems = lib.wf_plan_elems(self._h)
+        out = arr()
+        _lib.check(lib.wf_plan_offsets(self._h, out), "wf_plan_offsets")
+        self.offsets = list(out)
+        t, r = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(lib.wf_plan_config(self._h, ctypes.byref(t), ctypes.byref(r)), "wf_plan_config")
+        self.tile, self.rows = t.value, r.value
+
+    def pack(self, mats) -> torch.Tensor:
+        """Packs a list of m_i x n_i tensors into one device buffer of the plan's layout."""
+        buf = torch.zeros(self.elems, dtype=self.dtype, device=self.device)
+        for o, x in zip(self.offsets, mats):
+            buf[o:o + x.numel()].copy_(x.reshape(-1))
+        return buf
+
+    def unpack(self, buf: torch.Tensor):
+        return [buf[o:o + m * n].view(m, n) for o, m, n in zip(self.offsets, self.ms, self.ns)]
+
+    def forward(self, C: torch.Tensor, table: bool = False, D: torch.Tensor | None = None,
+                scores: torch.Tensor | None = None):
+        if C.dtype != self.dtype or C.device != self.device or not C.is_contiguous() or C.numel() < self.elems:
+            raise ValueError("C must be a contiguous device buffer of the plan's dtype holding plan.elems elements")
+        if D is None and table:
+            D = torch.empty(self.elems, dtype=self.dtype, device=self.device)
+        if D is not None and (D.dtype != self.dtype or D.device != self.device or not D.is_contiguous()
+                              or D.numel() < self.elems):
+            raise ValueError("D must be a contiguous device buffer like C")
+        if scores is None:
+            scores = torch.empty(self.batch, dtype=self.dtype, device=self.device)
+        rc = _lib.load().wf_batch_forward(self._h, C.data_ptr(), D.data_ptr() if D is not None else None,
+                                          scores.data_ptr(), _stream(self.device))
+        _lib.check(rc, "wf_batch_forward")
+        return scores, D
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().wf_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def set_tile(tile: int) -> None:

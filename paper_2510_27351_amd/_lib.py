@@ -34,6 +34,19 @@ def load():
     lib.wf_forward.restype = ctypes.c_int
     lib.wf_backward.argtypes = [ctypes.c_int, i64, i64, p, i64, p, i32, p, i64, p, p, i64, p, i64, p]
     lib.wf_backward.restype = ctypes.c_int
+    pi64 = ctypes.POINTER(i64)
+    lib.wf_plan_create.argtypes = [ctypes.POINTER(p), ctypes.c_int, i32, pi64, pi64, pi64, i32, i32, p]
+    lib.wf_plan_create.restype = ctypes.c_int
+    lib.wf_plan_elems.argtypes = [p]
+    lib.wf_plan_elems.restype = i64
+    lib.wf_plan_offsets.argtypes = [p, pi64]
+    lib.wf_plan_offsets.restype = ctypes.c_int
+    lib.wf_plan_config.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.wf_plan_config.restype = ctypes.c_int
+    lib.wf_batch_forward.argtypes = [p, p, p, p, p]
+    lib.wf_batch_forward.restype = ctypes.c_int
+    lib.wf_plan_destroy.argtypes = [p]
+    lib.wf_plan_destroy.restype = None
     lib.wf_ckpt_elems.argtypes = [i64, i64, i32]
     lib.wf_ckpt_elems.restype = i64
     lib.wf_set_tile.argtypes = [i32]

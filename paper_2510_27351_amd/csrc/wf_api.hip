@@ -18,15 +18,6 @@
 namespace wf {
 namespace {
 
-struct DeviceWs {
-  Control* ctl = nullptr;     // device control block (zeroed, epoch = 1)
-  uint64_t* bnd = nullptr;    // tagged handoff words
-  size_t bnd_words = 0;
-  uint32_t* sel = nullptr;    // selection codes of the adjoint
-  size_t sel_words = 0;
-  int num_cus = 0;
-};
-
 std::mutex g_mu;
 std::vector<DeviceWs> g_ws;
 int g_tile_override = 0;
@@ -34,6 +25,8 @@ int g_tile_override = 0;
 uint64_t* g_trace = nullptr;
 int64_t g_trace_bands = 0;
 int g_trace_dev = -1;
+
+}  // namespace
 
 int ensure_ws(int dev, size_t words, DeviceWs** out) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -90,6 +83,8 @@ int elem_size(int dtype) {
 
 int words_per_elem(int dtype) { return dtype == WF_F64 ? 2 : 1; }
 
+namespace {
+
 // Tile width used when the caller has not forced one.
 int choose_tile(int64_t m, int64_t n) {
   if (g_tile_override) return g_tile_override;
@@ -102,10 +97,6 @@ int choose_tile(int64_t m, int64_t n) {
 }
 
 int64_t nbands(int64_t m) { return (m + kBand - 1) / kBand; }
-
-// Largest leading dimension, in bytes: a band of up to 128 rows is addressed with 32-bit
-// byte offsets.
-constexpr int64_t kMaxLd = ((int64_t)1 << 31) / 128 - 16;
 
 }  // namespace
 }  // namespace wf

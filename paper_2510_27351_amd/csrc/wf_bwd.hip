@@ -139,49 +139,95 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
   }
 }
 
+// Sub-chunks of C the selection loader keeps in flight in registers (two waves per
+// workgroup leave room for them).
 template <typename T>
-__device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const SelArgs& a, int band, int Ks) {
+struct SelPF {
+  static constexpr int PF = sizeof(T) == 4 ? 3 : 1;
+};
+
+// Issues the loads of sub-chunk k of C (16 lanes x 4 rows per vector, rows 0..63) and of
+// the row above the band for slots [64k, 64k+64).
+template <typename T>
+__device__ __forceinline__ void sel_load_sub(Vec4<T> (&x)[16], T& tv, __amdgpu_buffer_rsrc_t rsrc, int64_t ldc,
+                                             const T* top, int64_t n, int k) {
+  const int lane = threadIdx.x & 63;
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = 4 * v + (lane >> 4);
+    const int64_t c0 = (int64_t)kSub * k + 4 * (lane & 15) - i;
+    const uint32_t off = (uint32_t)(i * ldc + c0) * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 4) {
+      x[v] = __builtin_bit_cast(Vec4<T>, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
+    } else {
+      struct Hf { T y[2]; };
+      const Hf lo = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
+      const Hf hi = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(off + 16), 0, 0));
+      x[v].v[0] = lo.y[0]; x[v].v[1] = lo.y[1]; x[v].v[2] = hi.y[0]; x[v].v[3] = hi.y[1];
+    }
+  }
+  const int64_t j = (int64_t)kSub * k + lane;
+  tv = (top && j < n) ? top[j] : Elem<T>::inf();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void sel_store_sub(T* S, T* Tr, const Vec4<T> (&x)[16], T tv, int k, int rows,
+                                              int64_t n) {
   using C = BCfg<T>;
   using E = typename C::E;
   const int lane = threadIdx.x & 63;
+  const bool interior = rows == kBand && k > 0 && (int64_t)kSub * k + kSub <= n;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = 4 * v + (lane >> 4);
+    const int64_t c0 = (int64_t)kSub * k + 4 * (lane & 15) - i;
+    Vec4<T> y = x[v];
+    if (!interior) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i >= rows || c0 + e < 0 || c0 + e >= n) y.v[e] = E::inf();
+    }
+    *reinterpret_cast<Vec4<T>*>(S + i * C::PITCH + ((kSub * k + 4 * (lane & 15)) & C::MASK)) = y;
+  }
+  Tr[(kSub * k + lane) & C::MASK] = tv;
+}
+
+template <typename T>
+__device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const SelArgs& a, int band, int Ks) {
+  using C = BCfg<T>;
+  constexpr int PF = SelPF<T>::PF;
   const int64_t ldc = opaque(a.ldc), n = opaque(a.n), m = opaque(a.m);
   const int64_t row0 = (int64_t)band * kBand;
   const int rows = (int)(m - row0 < kBand ? m - row0 : kBand);
+  // Loads outside the band's rows (or columns outside [0, n) on the last row) return zeros
+  // from the range-checked buffer; sel_store_sub replaces them by +inf.
   const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(static_cast<const T*>(a.C) + row0 * ldc,
                                                 (uint32_t)(((rows - 1) * ldc + n) * (int64_t)sizeof(T)));
   const T* top = band > 0 ? static_cast<const T*>(a.top) + (int64_t)(band - 1) * a.ld_top : nullptr;
   uint64_t waited = 0;
-  for (int k = 0; k < Ks; ++k) {
-    const int older = k - C::RING / kSub;
-    if (older >= 0 && !lds_wait_ge<false>(&sh.steps, (uint32_t)(kSub * (older + 1)), &sh.abort, a.ctl, waited)) {
-      sh.abort = 1u;
-      return;
-    }
-    const bool interior = rows == kBand && k > 0 && (int64_t)kSub * k + kSub <= n;
+  Vec4<T> buf[PF][16];
+  T tv[PF];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = 4 * v + (lane >> 4);
-      const int64_t c0 = (int64_t)kSub * k + 4 * (lane & 15) - i;
-      const uint32_t off = (uint32_t)(i * ldc + c0) * (uint32_t)sizeof(T);
-      Vec4<T> x;
-      if constexpr (sizeof(T) == 4) {
-        x = __builtin_bit_cast(Vec4<T>, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
-      } else {
-        struct Hf { T y[2]; };
-        const Hf lo = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
-        const Hf hi = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(off + 16), 0, 0));
-        x.v[0] = lo.y[0]; x.v[1] = lo.y[1]; x.v[2] = hi.y[0]; x.v[3] = hi.y[1];
-      }
-      if (!interior) {
+  for (int p = 0; p < PF; ++p)
+    if (p < Ks) sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, p);
+  for (int k0 = 0; k0 < Ks; k0 += PF) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (i >= rows || c0 + e < 0 || c0 + e >= n) x.v[e] = E::inf();
+    for (int p = 0; p < PF; ++p) {
+      const int k = k0 + p;
+      if (k >= Ks) break;
+      // sub-chunk k reuses the ring slots of sub-chunk k - RING/64
+      const int older = k - C::RING / kSub;
+      if (older >= 0 &&
+          !lds_wait_ge<false>(&sh.steps, (uint32_t)(kSub * (older + 1)), &sh.abort, a.ctl, waited)) {
+        sh.abort = 1u;
+        return;
       }
-      *reinterpret_cast<Vec4<T>*>(S + i * C::PITCH + ((kSub * k + 4 * (lane & 15)) & C::MASK)) = x;
+      sel_store_sub<T>(S, Tr, buf[p], tv[p], k, rows, n);
+      lds_publish(&sh.loaded, (uint32_t)(k + 1));
+      if (k + PF < Ks) sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, k + PF);
     }
-    const int64_t j = (int64_t)kSub * k + lane;
-    Tr[(kSub * k + lane) & C::MASK] = (top && j < n) ? top[j] : E::inf();
-    lds_publish(&sh.loaded, (uint32_t)(k + 1));
   }
 }
 
@@ -293,11 +339,45 @@ __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* _
 }
 
 // wave 1: loader of gD (plus gscore on the last cell; zeros when gD is absent) and of the
-// selection words, one 64-slot sub-chunk at a time from the top slot down.
+// selection words, one 64-slot sub-chunk at a time from the top slot down.  The loads of
+// the next PF sub-chunks are in flight in registers while one is written to LDS.
+template <typename T>
+struct AdjPF {
+  static constexpr int PF = 1;                         // gD sub-chunks
+  static constexpr int PFS = 4;                        // selection-word sub-chunks
+};
+
+template <typename T>
+__device__ __forceinline__ void adj_load_g(Vec4<T> (&x)[16], __amdgpu_buffer_rsrc_t rsrc, int64_t ldg_, int k) {
+  const int lane = threadIdx.x & 63;
+  // recomputed per call: hoisted out of the loop, the 16 row offsets would stay live
+  const int64_t ldg = opaque(ldg_);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = 4 * v + (lane >> 4);
+    const int64_t c0 = (int64_t)kSub * k + 4 * (lane & 15) - i;
+    const uint32_t off = (uint32_t)(i * ldg + c0) * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 4) {
+      x[v] = __builtin_bit_cast(Vec4<T>, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
+    } else {
+      struct Hf { T y[2]; };
+      const Hf lo = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
+      const Hf hi = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(off + 16), 0, 0));
+      x[v].v[0] = lo.y[0]; x[v].v[1] = lo.y[1]; x[v].v[2] = hi.y[0]; x[v].v[3] = hi.y[1];
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
 template <typename T, int G>
 __device__ __forceinline__ void adj_loader(T* S, uint32_t* SelR, AdjShared& sh, const AdjArgs& a, int band, int Ks) {
   using C = BCfg<T>;
   using E = typename C::E;
+  constexpr int PF = AdjPF<T>::PF, PFS = AdjPF<T>::PFS;
+  static_assert(PFS % PF == 0, "prefetch depths must nest");
   const int lane = threadIdx.x & 63;
   const int64_t ldg = opaque(a.ldgd), n = opaque(a.n), m = opaque(a.m);
   const int64_t row0 = (int64_t)band * kBand;
@@ -311,53 +391,64 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* SelR, AdjShared& sh, 
   const bool has_last = last_row >= 0 && last_row < kBand && a.gscore != nullptr;
   const T gs = has_last ? *static_cast<const T*>(a.gscore) : E::zero();
   const int64_t last_slot = n - 1 + last_row;
+  const uint32_t* selp = a.sel + sel_index(band, Ks, 0, lane);  // + 256 words per sub-chunk
   uint64_t waited = 0;
-  for (int kr = 0; kr < Ks; ++kr) {
-    const int k = Ks - 1 - kr;  // sub-chunk (slots [64k, 64k+64))
-    const int older = kr - C::RING / kSub;
-    if (older >= 0 && (!lds_wait_ge<false>(&sh.ctr[3], (uint32_t)(older + 1), &sh.abort, a.ctl, waited) ||
-                       !lds_wait_ge<false>(&sh.ctr[4], (uint32_t)((kSub / G) * (older + 1)), &sh.abort, a.ctl,
-                                           waited))) {
-      sh.abort = 1u;
-      return;
-    }
-    const bool interior = rows == kBand && k > 0 && (int64_t)kSub * k + kSub <= n;
+  Vec4<T> gbuf[PF][16];
+  v4i_t sbuf[PFS];
+  // reverse order: the kr-th sub-chunk processed is k = Ks-1-kr
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = 4 * v + (lane >> 4);
-      const int slot = kSub * k + 4 * (lane & 15);
-      const int64_t c0 = (int64_t)slot - i;
-      Vec4<T> x;
-      if (has_g) {
-        const uint32_t off = (uint32_t)(i * ldg + c0) * (uint32_t)sizeof(T);
-        if constexpr (sizeof(T) == 4) {
-          x = __builtin_bit_cast(Vec4<T>, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
+  for (int p = 0; p < PFS; ++p)
+    if (p < Ks) sbuf[p] = __builtin_nontemporal_load(reinterpret_cast<const v4i_t*>(selp + (int64_t)(Ks - 1 - p) * 256));
+  if (has_g) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+      if (p < Ks) adj_load_g<T>(gbuf[p], rsrc, ldg, Ks - 1 - p);
+  }
+  for (int kr0 = 0; kr0 < Ks; kr0 += PFS) {
+#pragma unroll
+    for (int p = 0; p < PFS; ++p) {
+      const int kr = kr0 + p;
+      if (kr >= Ks) break;
+      const int k = Ks - 1 - kr;  // sub-chunk (slots [64k, 64k+64))
+      const int older = kr - C::RING / kSub;
+      if (older >= 0 && (!lds_wait_ge<false>(&sh.ctr[3], (uint32_t)(older + 1), &sh.abort, a.ctl, waited) ||
+                         !lds_wait_ge<false>(&sh.ctr[4], (uint32_t)((kSub / G) * (older + 1)), &sh.abort, a.ctl,
+                                             waited))) {
+        sh.abort = 1u;
+        return;
+      }
+      const bool interior = rows == kBand && k > 0 && (int64_t)kSub * k + kSub <= n;
+      Vec4<T>(&gx)[16] = gbuf[p % PF];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = 4 * v + (lane >> 4);
+        const int slot = kSub * k + 4 * (lane & 15);
+        const int64_t c0 = (int64_t)slot - i;
+        Vec4<T> x;
+        if (has_g) {
+          x = gx[v];
+          if (!interior) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (i >= rows || c0 + e < 0 || c0 + e >= n) x.v[e] = E::zero();
+          }
         } else {
-          struct Hf { T y[2]; };
-          const Hf lo = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
-          const Hf hi = __builtin_bit_cast(Hf, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(off + 16), 0, 0));
-          x.v[0] = lo.y[0]; x.v[1] = lo.y[1]; x.v[2] = hi.y[0]; x.v[3] = hi.y[1];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x.v[e] = E::zero();
         }
-        if (!interior) {
+        if (has_last && i == (int)last_row) {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (i >= rows || c0 + e < 0 || c0 + e >= n) x.v[e] = E::zero();
+            if (last_slot == slot + e) x.v[e] = E::add(x.v[e], gs);
         }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) x.v[e] = E::zero();
+        *reinterpret_cast<Vec4<T>*>(S + i * C::PITCH + (slot & C::MASK)) = x;
       }
-      if (has_last && i == (int)last_row) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (last_slot == slot + e) x.v[e] = E::add(x.v[e], gs);
-      }
-      *reinterpret_cast<Vec4<T>*>(S + i * C::PITCH + (slot & C::MASK)) = x;
+      *reinterpret_cast<v4i_t*>(SelR + lane * C::SPITCH + ((4 * k) & (C::SW - 1))) = sbuf[p];
+      lds_publish(&sh.ctr[0], (uint32_t)(kr + 1));
+      if (kr + PFS < Ks)
+        sbuf[p] = __builtin_nontemporal_load(reinterpret_cast<const v4i_t*>(selp + (int64_t)(k - PFS) * 256));
+      if (has_g && kr + PF < Ks) adj_load_g<T>(gx, rsrc, ldg, k - PF);
     }
-    typedef int v4i __attribute__((ext_vector_type(4)));
-    const v4i w = *reinterpret_cast<const v4i*>(a.sel + sel_index(band, Ks, k, lane));
-    *reinterpret_cast<v4i*>(SelR + lane * C::SPITCH + ((4 * k) & (C::SW - 1))) = w;
-    lds_publish(&sh.ctr[0], (uint32_t)(kr + 1));
   }
 }
 

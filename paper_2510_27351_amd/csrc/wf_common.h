@@ -23,6 +23,11 @@ __device__ __forceinline__ uint32_t dpp_shr1_u32(uint32_t src, uint32_t old) {
   // wave_shr:1 -- lane r receives lane r-1's value; lane 0 keeps 'old' (bound_ctrl off).
   return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xf, 0xf, false);
 }
+__device__ __forceinline__ uint32_t dpp_shr1z_u32(uint32_t src) {
+  // wave_shr:1 with bound_ctrl: lane 0 reads zero.  Feeding an add, the move folds into a
+  // DPP add.
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)src, 0x138, 0xf, 0xf, true);
+}
 
 template <>
 struct Elem<float> {
@@ -34,6 +39,9 @@ struct Elem<float> {
   __device__ static __forceinline__ float shr1(float src, float old) {
     return __builtin_bit_cast(float, dpp_shr1_u32(__builtin_bit_cast(uint32_t, src),
                                                   __builtin_bit_cast(uint32_t, old)));
+  }
+  __device__ static __forceinline__ float shr1z(float src) {
+    return __builtin_bit_cast(float, dpp_shr1z_u32(__builtin_bit_cast(uint32_t, src)));
   }
   __device__ static __forceinline__ float min3(float a, float b, float c) {
     return __builtin_fminf(__builtin_fminf(a, b), c);
@@ -53,6 +61,7 @@ struct Elem<int32_t> {
   __device__ static __forceinline__ int32_t shr1(int32_t src, int32_t old) {
     return (int32_t)dpp_shr1_u32((uint32_t)src, (uint32_t)old);
   }
+  __device__ static __forceinline__ int32_t shr1z(int32_t src) { return (int32_t)dpp_shr1z_u32((uint32_t)src); }
   __device__ static __forceinline__ int32_t min3(int32_t a, int32_t b, int32_t c) {
     int32_t x = a < b ? a : b;
     return x < c ? x : c;
@@ -77,6 +86,11 @@ struct Elem<double> {
     uint32_t hi = dpp_shr1_u32((uint32_t)(s >> 32), (uint32_t)(o >> 32));
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
   }
+  __device__ static __forceinline__ double shr1z(double src) {
+    const uint64_t s = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = dpp_shr1z_u32((uint32_t)s), hi = dpp_shr1z_u32((uint32_t)(s >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  }
   __device__ static __forceinline__ double min3(double a, double b, double c) {
     return __builtin_fmin(__builtin_fmin(a, b), c);
   }
@@ -89,6 +103,19 @@ struct Elem<double> {
     return __builtin_bit_cast(double, ((uint64_t)w[1] << 32) | w[0]);
   }
 };
+
+// Value of lane 'l' (wave-uniform) in every lane.
+template <typename T>
+__device__ __forceinline__ T lane_value(T x, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
 
 // Four consecutive elements, as moved by one 16-byte (float/int) or two 16-byte (double)
 // LDS accesses.

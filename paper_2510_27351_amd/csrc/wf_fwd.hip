@@ -110,42 +110,62 @@ __device__ __forceinline__ uint64_t load_ready(const Shared& sh) {
 template <typename T, int G, int R>
 struct ComputeState {
   T X[R];   // previous value of each sub-band (W of the next cell)
-  T NW[R];  // previous N of each sub-band
-  T Q[R];   // for k >= 1: lane 63 of sub-band k-1 two steps back (rotated to lane 0)
+  T Xp;     // sub-band 0: the value before that (lane r-1's is the NW of the next cell)
+  T NW[R];  // k >= 1: previous N of the sub-band
+  T Q[R];   // k >= 1: lane 63 of sub-band k-1 two steps back (rotated to lane 0)
+};
+
+// Per 4-step group: C of every sub-band, and for sub-band 0 the two operands that differ in
+// lane 0 (row 0 of the band), where the top ring supplies C + NW and C + N precomputed.
+template <typename T, int G, int R>
+struct GroupRegs {
+  Vec4<T> c[R];
+  Vec4<T> ca, cb;
 };
 
 template <typename T, int G, int R>
 struct UnitRegs {
-  Vec4<T> c[2][R];  // C of the unit's first two groups, per sub-band
-  Vec4<T> t[2];     // top values of the unit's first two groups
+  GroupRegs<T, G, R> g[2];  // the unit's first two groups
 };
 
 template <typename T, int G, int R>
-__device__ __forceinline__ void load_group(const T* __restrict__ S, const T* __restrict__ Tr, int slot, int lane,
-                                           Vec4<T> (&c)[R], Vec4<T>& t) {
+__device__ __forceinline__ void load_group(const T* __restrict__ S, const T* __restrict__ rowA,
+                                           const T* __restrict__ rowB, int slot, int lane, GroupRegs<T, G, R>& r) {
   using C = FwdCfg<T, G, R>;
 #pragma unroll
-  for (int k = 0; k < R; ++k) c[k] = *reinterpret_cast<const Vec4<T>*>(S + (k * kBand + lane) * C::PITCH + slot);
-  t = *reinterpret_cast<const Vec4<T>*>(Tr + slot);
+  for (int k = 0; k < R; ++k) r.c[k] = *reinterpret_cast<const Vec4<T>*>(S + (k * kBand + lane) * C::PITCH + slot);
+  r.ca = *reinterpret_cast<const Vec4<T>*>(rowA + slot);
+  r.cb = *reinterpret_cast<const Vec4<T>*>(rowB + slot);
 }
 
+// Four steps.  Sub-band 0 uses  X = min(C + NW, C + W, C + N): rounding is monotone, so
+// this equals C + min(NW, N, W) exactly, and the shifted operands enter through DPP adds
+// (lane 0 reads zero and gets C + NW, C + N from the top ring), which leaves two dependent
+// instructions per step on the chain.  Sub-bands k >= 1 take their lane-0 inputs from
+// lane 63 of sub-band k-1 in registers and use the direct form.
 template <typename T, int G, int R>
-__device__ __forceinline__ void cells4(ComputeState<T, G, R>& st, const Vec4<T> (&c)[R], const Vec4<T>& t,
-                                       Vec4<T> (&out)[R]) {
+__device__ __forceinline__ void cells4(ComputeState<T, G, R>& st, const GroupRegs<T, G, R>& r, Vec4<T> (&out)[R]) {
   using E = Elem<T>;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     T N[R], Qn[R];
-    N[0] = E::shr1(st.X[0], t.v[q]);  // lane 0 takes the row above the band
 #pragma unroll
     for (int k = 1; k < R; ++k) {
       N[k] = E::shr1(st.X[k], st.Q[k]);  // lane 0 takes lane 63 of sub-band k-1
       Qn[k] = ror1(st.X[k - 1]);         // ... for the next step
     }
+    {
+      const T a = E::add(r.ca.v[q], E::shr1z(st.Xp));
+      const T w = E::add(r.c[0].v[q], st.X[0]);
+      const T b = E::add(r.cb.v[q], E::shr1z(st.X[0]));
+      st.Xp = st.X[0];
+      st.X[0] = E::min3(a, w, b);
+      out[0].v[q] = st.X[0];
+    }
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
+    for (int k = 1; k < R; ++k) {
       const T v = E::min3(st.NW[k], N[k], st.X[k]);
-      st.X[k] = E::add(c[k].v[q], v);
+      st.X[k] = E::add(r.c[k].v[q], v);
       st.NW[k] = N[k];
       out[k].v[q] = st.X[k];
     }
@@ -174,7 +194,8 @@ __device__ __forceinline__ bool unit_ready(uint64_t ready, int u, Shared& sh, Co
 // of each later group are issued two groups ahead, and the last two groups issue the reads
 // of unit u+1 into 'out' (after checking that unit u+1 is ready).
 template <typename T, int G, int R>
-__device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restrict__ Tr, Shared& sh, Control* ctl,
+__device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restrict__ rowA, const T* __restrict__ rowB,
+                                             Shared& sh, Control* ctl,
                                              int u, int Us, ComputeState<T, G, R>& st, const UnitRegs<T, G, R>& in,
                                              UnitRegs<T, G, R>& out, uint32_t& stall_c, uint32_t& stall_t,
                                              uint64_t& waited, bool trace) {
@@ -186,27 +207,23 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
   const bool has_next = u + 1 < Us;
   const uint64_t ready = load_ready(sh);  // for unit u+1, used two groups before the end
   __builtin_amdgcn_sched_barrier(0);
-  Vec4<T> cv[NG + 2][R], tv[NG + 2];
+  GroupRegs<T, G, R> gr[NG + 2];
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-#pragma unroll
-    for (int k = 0; k < R; ++k) cv[p][k] = in.c[p][k];
-    tv[p] = in.t[p];
-  }
+  for (int p = 0; p < 2; ++p) gr[p] = in.g[p];
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (g + 2 < NG) {
-      load_group<T, G, R>(S, Tr, base + 4 * (g + 2), lane, cv[g + 2], tv[g + 2]);
+      load_group<T, G, R>(S, rowA, rowB, base + 4 * (g + 2), lane, gr[g + 2]);
     } else if (has_next) {
       if (g + 2 == NG) {
         __builtin_amdgcn_sched_barrier(0);
         if (!unit_ready<T, G, R>(ready, u + 1, sh, ctl, stall_c, stall_t, waited, trace)) return false;
         __builtin_amdgcn_sched_barrier(0);
       }
-      load_group<T, G, R>(S, Tr, next_base + 4 * (g + 2 - NG), lane, out.c[g + 2 - NG], out.t[g + 2 - NG]);
+      load_group<T, G, R>(S, rowA, rowB, next_base + 4 * (g + 2 - NG), lane, out.g[g + 2 - NG]);
     }
     Vec4<T> d[R];
-    cells4<T, G, R>(st, cv[g], tv[g], d);
+    cells4<T, G, R>(st, gr[g], d);
 #pragma unroll
     for (int k = 0; k < R; ++k) *reinterpret_cast<Vec4<T>*>(S + (k * kBand + lane) * C::PITCH + base + 4 * g) = d[k];
   }
@@ -217,7 +234,8 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
 
 template <typename T, int G, int R>
 __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restrict__ Tr, Shared& sh, Control* ctl,
-                                             int band, int Us, uint64_t* trace) {
+                                             int Us, uint64_t* trace) {
+  using C = FwdCfg<T, G, R>;
   using E = Elem<T>;
   const int lane = threadIdx.x & 63;
   ComputeState<T, G, R> st;
@@ -227,7 +245,10 @@ __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restr
     st.NW[k] = E::inf();
     st.Q[k] = E::inf();
   }
-  if (lane == 0 && band == 0) st.NW[0] = E::zero();  // virtual corner D[-1][-1] = 0
+  st.Xp = E::inf();
+  // lane 0 reads C + NW and C + N of row 0 from the top ring (TA, TB), the others their C row
+  const T* rowA = lane == 0 ? Tr : S + lane * C::PITCH;
+  const T* rowB = lane == 0 ? Tr + C::RING : S + lane * C::PITCH;
   uint32_t stall_c = 0, stall_t = 0;
   uint64_t t_first = 0, waited = 0;
   const bool tr = trace != nullptr;
@@ -238,19 +259,19 @@ __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restr
   }
   if (tr) t_first = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
-  for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, Tr, 4 * p, lane, P.c[p], P.t[p]);
+  for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, rowA, rowB, 4 * p, lane, P.g[p]);
   // Units in pairs, so the next unit's prefetched registers alternate between P and Q
   // without copies.
   int u = 0;
   for (; u + 1 < Us; u += 2) {
-    if (!compute_unit<T, G, R>(S, Tr, sh, ctl, u, Us, st, P, Q, stall_c, stall_t, waited, tr) ||
-        !compute_unit<T, G, R>(S, Tr, sh, ctl, u + 1, Us, st, Q, P, stall_c, stall_t, waited, tr)) {
+    if (!compute_unit<T, G, R>(S, rowA, rowB, sh, ctl, u, Us, st, P, Q, stall_c, stall_t, waited, tr) ||
+        !compute_unit<T, G, R>(S, rowA, rowB, sh, ctl, u + 1, Us, st, Q, P, stall_c, stall_t, waited, tr)) {
       sh.abort = 1u;
       return;
     }
     if (tr && u == 62 / G) trace[16] = __builtin_amdgcn_s_memrealtime();
   }
-  if (u < Us && !compute_unit<T, G, R>(S, Tr, sh, ctl, u, Us, st, P, Q, stall_c, stall_t, waited, tr)) {
+  if (u < Us && !compute_unit<T, G, R>(S, rowA, rowB, sh, ctl, u, Us, st, P, Q, stall_c, stall_t, waited, tr)) {
     sh.abort = 1u;
     return;
   }
@@ -365,14 +386,17 @@ __device__ __forceinline__ void loader_band(T* S, Shared& sh, const FwdArgs& a, 
 // ---------------------------------------------------------------------------------------
 // wave 2: top boundary poller, G columns per unit
 template <typename T, int G, int R>
-__device__ __forceinline__ void top_band(T* Tr, Shared& sh, const FwdArgs& a, int band, int Ut, uint32_t epoch,
-                                         uint64_t* tr) {
+__device__ __forceinline__ void top_band(const T* S, T* Tr, Shared& sh, const FwdArgs& a, int band, int Ut,
+                                         uint32_t epoch, uint64_t* tr) {
   using C = FwdCfg<T, G, R>;
   using E = typename C::E;
   constexpr int W = E::W;
   const int lane = threadIdx.x & 63;
   const int64_t n = opaque(a.n);
   uint64_t waited = 0;
+  // top value of the column before the unit's first: the virtual corner D[-1][-1] = 0 for
+  // the first band, D[row0-1][-1] = +inf for the others
+  T last = band == 0 ? E::zero() : E::inf();
   for (int u = 0; u < Ut; ++u) {
     // the top ring slot of column j is read at step j and reused RING steps later
     const int64_t need_steps = (int64_t)G * u + G - C::RING;
@@ -424,7 +448,22 @@ __device__ __forceinline__ void top_band(T* Tr, Shared& sh, const FwdArgs& a, in
       }
       if (mine) val = E::from_words(w);
     }
-    if (lane < G) Tr[(G * u + lane) & C::MASK] = val;
+    // Row 0's C at these columns (slot = column) must be in LDS before its sums are formed.
+    const uint32_t need_c = (uint32_t)((G * u + G - 1) / kSub + 1);
+    if (!lds_wait_ge(&sh.ctr[0], need_c, &sh.abort, a.ctl, waited)) {
+      sh.abort = 1u;
+      return;
+    }
+    const T nw = E::shr1(val, last);  // top value one column to the left
+    last = lane_value(val, G - 1);
+    if (lane < G) {
+      // TA = C + NW and TB = C + N of row 0, the lane-0 operands of the compute wave
+      const int slot = (G * u + lane) & C::MASK;
+      const T c0 = S[slot];
+      const bool real = j < n;
+      Tr[slot] = real ? E::add(c0, nw) : E::inf();
+      Tr[C::RING + slot] = real ? E::add(c0, val) : E::inf();
+    }
     lds_signal(&sh.ctr[1], (uint32_t)(u + 1));
     if (tr && u == 0 && lane == 0) tr[15] = __builtin_amdgcn_s_memrealtime();
   }
@@ -582,21 +621,42 @@ __device__ __forceinline__ void publish_band(const T* S, Shared& sh, const FwdAr
 }
 
 // ---------------------------------------------------------------------------------------
+// One band of one instance, all five roles.  The LDS counters must be zero on entry.
 template <typename T, int G, int R>
-__global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
+__device__ __forceinline__ void run_band(T* S, T* Tr, Shared& sh, const FwdArgs& a, int band, uint32_t epoch,
+                                         uint64_t* tr) {
   using C = FwdCfg<T, G, R>;
-  __shared__ Vec4<T> S4[C::H * C::PITCH / 4];
-  __shared__ Vec4<T> Tr4[C::RING / 4];
-  __shared__ Shared sh;
-  T* S = reinterpret_cast<T*>(S4);
-  T* Tr = reinterpret_cast<T*>(Tr4);
   const int wave = threadIdx.x >> 6;
-  Control* ctl = a.ctl;
-  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // steps of a band: n + skew(H-1), rounded up to whole 64-slot sub-chunks
   const int Ks = (int)((a.n + C::skew(C::H - 1) + kSub - 1) / kSub);  // C sub-chunks
   const int Us = Ks * C::GPS;                                          // compute / publish units
   const int Ut = (int)((a.n + G - 1) / G);                             // top units holding real columns
+  if (wave == 0) {
+    compute_band<T, G, R>(S, Tr, sh, a.ctl, Us, tr);
+  } else if (wave == 1) {
+    loader_band<T, G, R>(S, sh, a, band, Ks, tr);
+  } else if (wave == 2) {
+    top_band<T, G, R>(S, Tr, sh, a, band, Ut, epoch, tr);
+    // Top units beyond the last real column hold no values any real cell reads; mark
+    // them loaded so that the compute wave's readiness test stays one comparison.
+    if ((threadIdx.x & 63) == 0 && sh.abort == 0u) lds_signal(&sh.ctr[1], 0x7fffffffu);
+  } else if (wave == 3) {
+    store_band<T, G, R>(S, sh, a, band, Ks, tr);
+  } else {
+    publish_band<T, G, R>(S, sh, a, band, Us, epoch, tr);
+  }
+}
+
+template <typename T, int G, int R>
+__global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
+  using C = FwdCfg<T, G, R>;
+  __shared__ Vec4<T> S4[C::H * C::PITCH / 4];
+  __shared__ Vec4<T> Tr4[2 * C::RING / 4];
+  __shared__ Shared sh;
+  T* S = reinterpret_cast<T*>(S4);
+  T* Tr = reinterpret_cast<T*>(Tr4);
+  Control* ctl = a.ctl;
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (threadIdx.x == 0) sh.abort = 0u;
   for (;;) {
     if (threadIdx.x < 6) sh.ctr[threadIdx.x] = 0u;
@@ -611,21 +671,50 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
       tr[6] = xcc;
       tr[7] = blockIdx.x;
     }
-    if (wave == 0) {
-      compute_band<T, G, R>(S, Tr, sh, ctl, band, Us, tr);
-    } else if (wave == 1) {
-      loader_band<T, G, R>(S, sh, a, band, Ks, tr);
-    } else if (wave == 2) {
-      top_band<T, G, R>(Tr, sh, a, band, Ut, epoch, tr);
-      // Top units beyond the last real column hold no values any real cell reads; mark
-      // them loaded so that the compute wave's readiness test stays one comparison.
-      if ((threadIdx.x & 63) == 0 && sh.abort == 0u) lds_signal(&sh.ctr[1], 0x7fffffffu);
-    } else if (wave == 3) {
-      store_band<T, G, R>(S, sh, a, band, Ks, tr);
-    } else {
-      publish_band<T, G, R>(S, sh, a, band, Us, epoch, tr);
-    }
+    run_band<T, G, R>(S, Tr, sh, a, band, epoch, tr);
     if (tr && threadIdx.x == 3 * 64) tr[3] = __builtin_amdgcn_s_memrealtime();
+    __syncthreads();
+  }
+  finish_launch(ctl, epoch);
+}
+
+// Ragged batch: work items (instance, band) are claimed in list order; the host orders the
+// list so that every band comes after the band above it of the same instance (and
+// instances by decreasing critical path), so a claimed band only ever waits for bands
+// that were claimed before it and are running or done.
+template <typename T, int G, int R>
+__global__ __launch_bounds__(kThreads, 1) void fwd_batch_kernel(BatchArgs b) {
+  using C = FwdCfg<T, G, R>;
+  __shared__ Vec4<T> S4[C::H * C::PITCH / 4];
+  __shared__ Vec4<T> Tr4[2 * C::RING / 4];
+  __shared__ Shared sh;
+  T* S = reinterpret_cast<T*>(S4);
+  T* Tr = reinterpret_cast<T*>(Tr4);
+  Control* ctl = b.ctl;
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) sh.abort = 0u;
+  for (;;) {
+    if (threadIdx.x < 6) sh.ctr[threadIdx.x] = 0u;
+    claim_next(ctl, &sh.item, &sh.abort);
+    const uint32_t item = sh.item;
+    if (item >= (uint32_t)b.n_items || sh.abort != 0u) break;
+    const BatchItem it = b.items[item];
+    const BatchInst in = b.inst[it.inst];
+    FwdArgs a;
+    a.C = static_cast<const T*>(b.C) + in.off;
+    a.D = b.D ? static_cast<T*>(b.D) + in.off : nullptr;
+    a.score = static_cast<T*>(b.scores) + it.inst;
+    a.ckpt = nullptr;
+    a.ldc = in.n;
+    a.ldd = in.n;
+    a.m = in.m;
+    a.n = in.n;
+    a.ckpt_k = 0;
+    a.nb = in.nb;
+    a.ctl = ctl;
+    a.bnd = b.bnd + in.bnd_off;
+    a.trace = nullptr;
+    run_band<T, G, R>(S, Tr, sh, a, it.band, epoch, nullptr);
     __syncthreads();
   }
   finish_launch(ctl, epoch);
@@ -642,13 +731,22 @@ hipError_t launch_t(int tile, const FwdArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-// 64-row sub-bands per band for the 4-byte types.  One is the fastest at 16384 x 16384 on
-// MI355X (R = 2 halves the handoffs but doubles the per-step work of the compute wave and
-// leaves half of the compute units idle at 256 bands); double always uses one.
-#ifndef WF_FWD_ROWS
-#define WF_FWD_ROWS 1
-#endif
-constexpr int kRowsF = WF_FWD_ROWS;
+template <typename T, int R>
+hipError_t launch_batch_t(int tile, const BatchArgs& b, int grid, hipStream_t s) {
+  switch (tile) {
+    case 16: hipLaunchKernelGGL((fwd_batch_kernel<T, 16, R>), dim3(grid), dim3(kThreads), 0, s, b); break;
+    case 32: hipLaunchKernelGGL((fwd_batch_kernel<T, 32, R>), dim3(grid), dim3(kThreads), 0, s, b); break;
+    case 64: hipLaunchKernelGGL((fwd_batch_kernel<T, 64, R>), dim3(grid), dim3(kThreads), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// 64-row sub-bands per band of the single-instance sweep for the 4-byte types.  One is the
+// fastest at 16384 x 16384 on MI355X (two halve the handoffs but double the compute wave's
+// work per step and leave half of the compute units idle at 256 bands); double always
+// uses one.  The batch sweep lets its autotuner choose one or two.
+constexpr int kRowsF = 1;
 
 }  // namespace
 
@@ -659,6 +757,19 @@ hipError_t launch_forward(int dtype, int tile, const FwdArgs& a, int grid, hipSt
     case 0: return launch_t<float, kRowsF>(tile, a, grid, s);
     case 1: return launch_t<double, 1>(tile, a, grid, s);
     case 2: return launch_t<int32_t, kRowsF>(tile, a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_forward_batch(int dtype, int tile, int rows, const BatchArgs& b, int grid, hipStream_t s) {
+  if (rows == 2 && dtype != 1) {
+    return dtype == 0 ? launch_batch_t<float, 2>(tile, b, grid, s) : launch_batch_t<int32_t, 2>(tile, b, grid, s);
+  }
+  if (rows != 1) return hipErrorInvalidValue;
+  switch (dtype) {
+    case 0: return launch_batch_t<float, 1>(tile, b, grid, s);
+    case 1: return launch_batch_t<double, 1>(tile, b, grid, s);
+    case 2: return launch_batch_t<int32_t, 1>(tile, b, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

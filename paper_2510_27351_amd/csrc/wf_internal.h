@@ -89,12 +89,61 @@ struct AdjArgs {
   uint64_t* trace;
 };
 
+// Ragged batch of instances packed in one buffer.  Instance i is an m x n row-major matrix
+// with leading dimension n at element offset 'off' of C (and of D); its handoff words start
+// at word bnd_off of the plan's buffer.
+struct BatchInst {
+  int64_t off;
+  int64_t m, n;
+  int64_t bnd_off;
+  int32_t nb;       // bands of the instance
+  int32_t pad;
+};
+struct BatchItem {
+  int32_t inst;
+  int32_t band;
+};
+struct BatchArgs {
+  const void* C;
+  void* D;              // may be null (scores only)
+  void* scores;         // one element per instance
+  const BatchInst* inst;
+  const BatchItem* items;
+  int32_t n_items;
+  int32_t pad;
+  Control* ctl;
+  uint64_t* bnd;
+};
+
 // Host-side launchers (defined in wf_fwd.hip).  'tile' is 16, 32 or 64.
 hipError_t launch_forward(int dtype, int tile, const FwdArgs& a, int grid, hipStream_t s);
-// Rows per band of the forward sweep for a dtype (128 for 4-byte elements, 64 for double).
+// Rows per band of the single-instance forward sweep for a dtype.
 int forward_band_rows(int dtype);
+// Batch sweep; 'rows' = 64-row sub-bands per band: 1, or 2 for the 4-byte types.
+hipError_t launch_forward_batch(int dtype, int tile, int rows, const BatchArgs& b, int grid, hipStream_t s);
 // Adjoint launchers (defined in wf_bwd.hip), float (dtype 0) and double (dtype 1) only.
 hipError_t launch_select(int dtype, const SelArgs& a, int grid, hipStream_t s);
 hipError_t launch_adjoint(int dtype, int tile, const AdjArgs& a, int grid, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Host runtime (defined in wf_api.hip).
+
+// Per-device workspace, created on the first call on a device and grown on demand.
+struct DeviceWs {
+  Control* ctl = nullptr;     // device control block (zeroed, epoch = 1)
+  uint64_t* bnd = nullptr;    // tagged handoff words
+  size_t bnd_words = 0;
+  uint32_t* sel = nullptr;    // selection codes of the adjoint
+  size_t sel_words = 0;
+  int num_cus = 0;
+};
+// Returns the workspace of device 'dev' with at least 'words' handoff words.
+int ensure_ws(int dev, size_t words, DeviceWs** out);
+int elem_size(int dtype);       // bytes per element, 0 for an invalid dtype
+int words_per_elem(int dtype);  // 32-bit payload words per element in the handoff words
+
+// Largest leading dimension, in bytes: a band of up to 128 rows is addressed with 32-bit
+// byte offsets.
+constexpr int64_t kMaxLd = ((int64_t)1 << 31) / 128 - 16;
 
 }  // namespace wf

@@ -1,0 +1,420 @@
+// Ragged-batch plans (declared in include/wf.h): a device work list over many instances of
+// different sizes, swept by one persistent launch that is captured once in a hipGraph and
+// replayed, plus the autotuner that picks the tile width and the rows per band.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/wf.h"
+#include "wf_internal.h"
+
+using namespace wf;
+
+struct wf_plan {
+  int dtype = 0;
+  int dev = 0;
+  int32_t batch = 0;
+  std::vector<int64_t> m, n, off;
+  int64_t elems = 0;
+  int tile = 0, rows = 0;         // the configuration in use
+  int num_cus = 0;
+  Control* ctl = nullptr;         // the device workspace's control block (shared, ordered)
+  BatchInst* inst = nullptr;      // device copy of the instance table for 'rows'
+  BatchItem* items = nullptr;     // device work list for 'rows'
+  int32_t n_items = 0;
+  uint64_t* bnd = nullptr;        // handoff words (sized for one row per band, the larger)
+  hipStream_t cap = nullptr;      // private stream used only to capture the graph
+  hipGraphExec_t exec = nullptr;  // captured launch, valid for the pointers below
+  const void* g_C = nullptr;
+  void* g_D = nullptr;
+  void* g_scores = nullptr;
+};
+
+namespace {
+
+// Work list for bands of 64*rows rows.  Items are ordered band index first: every band-0
+// item of every instance, then every band-1 item, and so on; within one band index,
+// instances with more bands left come first.  A band therefore always follows the band
+// above it of the same instance (the persistent workgroups can never wait on an unclaimed
+// item), and by the time it is claimed the band above has usually been running for a
+// whole round of the grid, so little time is lost to pipeline fill.
+void build_work(const wf_plan& p, int rows, std::vector<BatchInst>& inst, std::vector<BatchItem>& items,
+                size_t& bnd_words) {
+  const int64_t H = (int64_t)kBand * rows;
+  const int W = words_per_elem(p.dtype);
+  inst.resize(p.batch);
+  bnd_words = 0;
+  int32_t max_nb = 0;
+  for (int32_t i = 0; i < p.batch; ++i) {
+    BatchInst& b = inst[i];
+    b.off = p.off[i];
+    b.m = p.m[i];
+    b.n = p.n[i];
+    b.nb = (int32_t)((p.m[i] + H - 1) / H);
+    b.pad = 0;
+    b.bnd_off = (int64_t)bnd_words;
+    bnd_words += (size_t)(b.nb - 1) * (size_t)p.n[i] * W;
+    max_nb = std::max(max_nb, b.nb);
+  }
+  std::vector<int32_t> order(p.batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    if (inst[x].nb != inst[y].nb) return inst[x].nb > inst[y].nb;
+    return inst[x].n > inst[y].n;
+  });
+  items.clear();
+  for (int32_t band = 0; band < max_nb; ++band)
+    for (int32_t i : order)
+      if (band < inst[i].nb) items.push_back(BatchItem{i, band});
+  if (bnd_words == 0) bnd_words = 1;
+}
+
+int upload_work(wf_plan& p, int rows) {
+  std::vector<BatchInst> inst;
+  std::vector<BatchItem> items;
+  size_t words = 0;
+  build_work(p, rows, inst, items, words);
+  if (p.inst) (void)hipFree(p.inst);
+  if (p.items) (void)hipFree(p.items);
+  p.inst = nullptr;
+  p.items = nullptr;
+  if (hipMalloc(&p.inst, inst.size() * sizeof(BatchInst)) != hipSuccess) { p.inst = nullptr; return WF_E_NOMEM; }
+  if (hipMalloc(&p.items, items.size() * sizeof(BatchItem)) != hipSuccess) { p.items = nullptr; return WF_E_NOMEM; }
+  if (hipMemcpy(p.inst, inst.data(), inst.size() * sizeof(BatchInst), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p.items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) != hipSuccess)
+    return WF_E_DEVICE;
+  p.n_items = (int32_t)items.size();
+  p.rows = rows;
+  return WF_OK;
+}
+
+hipError_t launch_plan(const wf_plan& p, const void* C, void* D, void* scores, hipStream_t s) {
+  BatchArgs b;
+  b.C = C;
+  b.D = D;
+  b.scores = scores;
+  b.inst = p.inst;
+  b.items = p.items;
+  b.n_items = p.n_items;
+  b.pad = 0;
+  b.ctl = p.ctl;
+  b.bnd = p.bnd;
+  const int grid = std::min(p.n_items, p.num_cus);
+  return launch_forward_batch(p.dtype, p.tile, p.rows, b, grid, s);
+}
+
+// ---------------------------------------------------------------------------------------
+// Autotuner cache: the best (tile, rows) per (device kind, dtype, shape list), kept for the
+// process and, when WF_TUNE_CACHE names a file, in that file (one "key tile rows" line per
+// entry, appended when a new entry is measured).
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
+bool g_tune_file_read = false;
+
+std::string tune_key(const wf_plan& p) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the shape list
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)p.batch);
+  for (int32_t i = 0; i < p.batch; ++i) {
+    mix((uint64_t)p.m[i]);
+    mix((uint64_t)p.n[i]);
+  }
+  char buf[96];
+  std::snprintf(buf, sizeof(buf), "cu%d-dt%d-b%d-%016llx", p.num_cus, p.dtype, (int)p.batch, (unsigned long long)h);
+  return buf;
+}
+
+bool tune_lookup(const std::string& key, int& tile, int& rows) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const char* path = std::getenv("WF_TUNE_CACHE");
+  if (path && !g_tune_file_read) {
+    g_tune_file_read = true;
+    if (FILE* f = std::fopen(path, "r")) {
+      char k[128];
+      int t, r;
+      while (std::fscanf(f, "%127s %d %d", k, &t, &r) == 3)
+        if ((t == 16 || t == 32 || t == 64) && (r == 1 || r == 2)) g_tune[k] = {t, r};
+      std::fclose(f);
+    }
+  }
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  tile = it->second.first;
+  rows = it->second.second;
+  return true;
+}
+
+void tune_store(const std::string& key, int tile, int rows) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = {tile, rows};
+  if (const char* path = std::getenv("WF_TUNE_CACHE")) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s %d %d\n", key.c_str(), tile, rows);
+      std::fclose(f);
+    }
+  }
+}
+
+// Times every allowed (tile, rows) on scratch buffers of the plan's size (the sweep's time
+// does not depend on the values) and keeps the fastest.  Synchronizes the stream.
+int autotune(wf_plan& p, int want_tile, int want_rows, hipStream_t s) {
+  const int es = elem_size(p.dtype);
+  const size_t bytes = (size_t)std::max<int64_t>(p.elems, 1) * es;
+  void* C = nullptr;
+  void* D = nullptr;
+  void* sc = nullptr;
+  int rc = WF_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float best = 1e30f;
+  int best_tile = 0, best_rows = 0;
+  if (hipMalloc(&C, bytes) != hipSuccess || hipMalloc(&D, bytes) != hipSuccess ||
+      hipMalloc(&sc, (size_t)p.batch * es) != hipSuccess) {
+    rc = WF_E_NOMEM;
+    goto done;
+  }
+  if (hipMemsetAsync(C, 0, bytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    rc = WF_E_DEVICE;
+    goto done;
+  }
+  for (int rows : {1, 2}) {
+    if (want_rows && rows != want_rows) continue;
+    if (rows == 2 && p.dtype == WF_F64) continue;
+    if ((rc = upload_work(p, rows)) != WF_OK) goto done;
+    for (int tile : {16, 32, 64}) {
+      if (want_tile && tile != want_tile) continue;
+      p.tile = tile;
+      float t_min = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        if (hipEventRecord(e0, s) != hipSuccess || launch_plan(p, C, D, sc, s) != hipSuccess ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = WF_E_DEVICE;
+          goto done;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = WF_E_DEVICE;
+          goto done;
+        }
+        if (rep > 0) t_min = std::min(t_min, ms);  // the first launch is a warm-up
+      }
+      if (t_min < best) {
+        best = t_min;
+        best_tile = tile;
+        best_rows = rows;
+      }
+    }
+  }
+  p.tile = best_tile;
+  p.rows = best_rows;
+done:
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  if (C) (void)hipFree(C);
+  if (D) (void)hipFree(D);
+  if (sc) (void)hipFree(sc);
+  return rc;
+}
+
+void free_plan(wf_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->inst) (void)hipFree(p->inst);
+  if (p->items) (void)hipFree(p->items);
+  if (p->bnd) (void)hipFree(p->bnd);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wf_plan_create(wf_plan** out, int dtype, int32_t batch, const int64_t* m, const int64_t* n,
+                   const int64_t* offsets, int32_t tile, int32_t rows, void* stream) {
+  if (!out) return WF_E_ARG;
+  *out = nullptr;
+  const int es = elem_size(dtype);
+  if (es == 0 || batch < 1 || !m || !n) return WF_E_ARG;
+  if (tile != 0 && tile != 16 && tile != 32 && tile != 64) return WF_E_ARG;
+  if (rows < 0 || rows > 2) return WF_E_ARG;
+  if (rows == 2 && dtype == WF_F64) return WF_E_UNSUPPORTED;
+  wf_plan* p = new wf_plan();
+  p->dtype = dtype;
+  p->batch = batch;
+  p->m.assign(m, m + batch);
+  p->n.assign(n, n + batch);
+  p->off.resize(batch);
+  // sizes, then the layout: the caller's offsets, or packed with 256-byte aligned starts
+  int64_t cells = 0;
+  for (int32_t i = 0; i < batch; ++i) {
+    if (m[i] < 1 || n[i] < 1 || n[i] > kMaxLd / es || m[i] > ((int64_t)1 << 40) || m[i] > INT64_MAX / n[i] ||
+        m[i] * n[i] > INT64_MAX / 4 - cells) {
+      delete p;
+      return WF_E_ARG;
+    }
+    cells += m[i] * n[i];
+  }
+  const int64_t align = 256 / es;
+  if (offsets) {
+    std::vector<int32_t> order(batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return offsets[x] < offsets[y]; });
+    int64_t end = 0;
+    for (int32_t i : order) {
+      // instances must not overlap: their tables are written in place of nothing shared
+      if (offsets[i] < end) {
+        delete p;
+        return WF_E_ARG;
+      }
+      end = offsets[i] + m[i] * n[i];
+      p->off[i] = offsets[i];
+    }
+    p->elems = end;
+  } else {
+    int64_t at = 0;
+    for (int32_t i = 0; i < batch; ++i) {
+      p->off[i] = at;
+      at += (m[i] * n[i] + align - 1) / align * align;
+    }
+    p->elems = at;
+  }
+  if (hipGetDevice(&p->dev) != hipSuccess) {
+    delete p;
+    return WF_E_DEVICE;
+  }
+  DeviceWs* ws = nullptr;
+  int rc = ensure_ws(p->dev, 1, &ws);
+  if (rc != WF_OK) {
+    delete p;
+    return rc;
+  }
+  p->ctl = ws->ctl;
+  p->num_cus = ws->num_cus;
+  // handoff words: the one-row-per-band layout needs the most
+  {
+    std::vector<BatchInst> inst;
+    std::vector<BatchItem> items;
+    size_t words = 0;
+    build_work(*p, 1, inst, items, words);
+    if (items.size() >= (size_t)INT32_MAX) {
+      delete p;
+      return WF_E_ARG;
+    }
+    if (hipMalloc(&p->bnd, words * sizeof(uint64_t)) != hipSuccess) {
+      p->bnd = nullptr;
+      free_plan(p);
+      return WF_E_NOMEM;
+    }
+    // tag 0 never equals a launch epoch, so zeroed words read as "not yet written"
+    if (hipMemset(p->bnd, 0, words * sizeof(uint64_t)) != hipSuccess) {
+      free_plan(p);
+      return WF_E_DEVICE;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int want_tile = tile, want_rows = rows;
+  if (tile == 0 || rows == 0) {
+    const std::string key = tune_key(*p);
+    int t = 0, r = 0;
+    if (tune_lookup(key, t, r) && (!tile || t == tile) && (!rows || r == rows)) {
+      want_tile = t;
+      want_rows = r;
+    } else {
+      rc = autotune(*p, tile, rows, s);
+      if (rc != WF_OK) {
+        free_plan(p);
+        return rc;
+      }
+      want_tile = p->tile;
+      want_rows = p->rows;
+      if (!tile && !rows) tune_store(key, want_tile, want_rows);
+    }
+  }
+  p->tile = want_tile;
+  rc = upload_work(*p, want_rows);
+  if (rc == WF_OK && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+    p->cap = nullptr;
+    rc = WF_E_DEVICE;
+  }
+  if (rc != WF_OK) {
+    free_plan(p);
+    return rc;
+  }
+  *out = p;
+  return WF_OK;
+}
+
+void wf_plan_destroy(wf_plan* plan) { free_plan(plan); }
+
+int64_t wf_plan_elems(const wf_plan* plan) { return plan ? plan->elems : -1; }
+
+int wf_plan_offsets(const wf_plan* plan, int64_t* offsets) {
+  if (!plan || !offsets) return WF_E_ARG;
+  std::memcpy(offsets, plan->off.data(), plan->off.size() * sizeof(int64_t));
+  return WF_OK;
+}
+
+int wf_plan_config(const wf_plan* plan, int32_t* tile, int32_t* rows) {
+  if (!plan) return WF_E_ARG;
+  if (tile) *tile = plan->tile;
+  if (rows) *rows = plan->rows;
+  return WF_OK;
+}
+
+int wf_batch_forward(wf_plan* plan, const void* C, void* D, void* scores, void* stream) {
+  if (!plan || !C || !scores) return WF_E_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  if (dev != plan->dev) return WF_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return WF_E_DEVICE;
+  if (cs == hipStreamCaptureStatusActive) {
+    // the caller is building a graph of its own: record the launch into it
+    return launch_plan(*plan, C, D, scores, s) == hipSuccess ? WF_OK : WF_E_DEVICE;
+  }
+  if (!plan->exec || plan->g_C != C || plan->g_D != D || plan->g_scores != scores) {
+    if (plan->exec) {
+      // an earlier replay may still be queued on some stream
+      if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+      (void)hipGraphExecDestroy(plan->exec);
+      plan->exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return WF_E_DEVICE;
+    const hipError_t le = launch_plan(*plan, C, D, scores, plan->cap);
+    const hipError_t ce = hipStreamEndCapture(plan->cap, &g);
+    if (le != hipSuccess || ce != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return WF_E_DEVICE;
+    }
+    const hipError_t ie = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      plan->exec = nullptr;
+      return WF_E_DEVICE;
+    }
+    plan->g_C = C;
+    plan->g_D = D;
+    plan->g_scores = scores;
+  }
+  return hipGraphLaunch(plan->exec, s) == hipSuccess ? WF_OK : WF_E_DEVICE;
+}
+
+}  // extern "C"
