@@ -156,9 +156,9 @@ int wf_set_tile(int32_t tile);
 
 /*
  * Tracing (for profiling the pipeline, off by default).  wf_trace_enable(B) allocates a
- * device buffer of B records on the current device; later forward calls on that device
- * whose band count is <= B fill record b for band b (a later call overwrites earlier
- * records).  wf_trace_enable(0) frees it.  wf_trace_fetch synchronizes the device and
+ * device buffer of B records on the current device; later forward calls and reverse sweeps
+ * of wf_backward on that device whose band count is <= B fill record b for band b (a later
+ * call overwrites earlier records).  wf_trace_enable(0) frees it.  wf_trace_fetch synchronizes the device and
  * copies up to max_bands records (8 uint64 each: claim time, first sub-chunk ready,
  * compute done, store done -- 100 MHz ticks --, sub-chunks the compute wave found not yet
  * loaded, sub-chunks whose top row had not yet arrived, XCC id, workgroup id) into 'host';

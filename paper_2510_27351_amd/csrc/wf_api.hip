@@ -245,7 +245,7 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   aa.Q = (int32_t)(4 * Ks);
   aa.ctl = ws->ctl;
   aa.bnd = ws->bnd;
-  aa.trace = nullptr;
+  aa.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
   e = launch_adjoint(dtype, choose_tile(m, n), aa, grid, st);
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
 }

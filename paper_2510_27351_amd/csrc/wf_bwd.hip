@@ -270,65 +270,161 @@ struct alignas(8) AdjShared {
   uint32_t abort;
 };
 
-__device__ __forceinline__ uint64_t adj_ready(const AdjShared& sh) {
-  return __hip_atomic_load(reinterpret_cast<const uint64_t*>(&sh.ctr[0]), __ATOMIC_RELAXED,
+// Both readiness counters of the compute wave in one 8-byte LDS read.  'zero' is 0, but
+// the compiler cannot tell: the value counts as per-lane data and is compared where it is
+// used, so the wave waits for it there rather than right after the read (where it would
+// also wait for every earlier LDS read, the prefetches).
+__device__ __forceinline__ uint64_t adj_ready(const AdjShared& sh, int zero) {
+  return __hip_atomic_load(reinterpret_cast<const uint64_t*>(&sh.ctr[0]) + zero, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int adj_opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  return z;
 }
 
 // wave 0: the reverse chain.  Slot group [b4, b4+4) is processed from b4+3 down to b4.
+// The LDS reads of a group (the upstream values, the band-below values and the selection
+// word) are issued PD groups ahead of their use: LDS latency under the other waves'
+// traffic is longer than one group's compute.
+template <typename T>
+struct AdjGroup {
+  Vec4<T> gv, bn, bnw;
+  uint32_t word;
+};
+
+template <typename T, int G>
+struct AdjCfg {
+  static constexpr int NG = G / 4;
+  static constexpr int PD = sizeof(T) == 4 ? 2 : 1;
+};
+
+template <typename T, int G>
+struct AdjUnitRegs {
+  AdjGroup<T> g[AdjCfg<T, G>::PD];
+};
+
+template <typename T>
+__device__ __forceinline__ void adj_load_group(const T* __restrict__ S, const uint32_t* __restrict__ SelR,
+                                               const T* __restrict__ Bn, const T* __restrict__ Bnw, int b4, int lane,
+                                               AdjGroup<T>& r) {
+  using C = BCfg<T>;
+  r.gv = *reinterpret_cast<const Vec4<T>*>(S + lane * C::PITCH + b4);
+  r.bn = *reinterpret_cast<const Vec4<T>*>(Bn + b4);
+  r.bnw = *reinterpret_cast<const Vec4<T>*>(Bnw + b4);
+  r.word = SelR[lane * C::SPITCH + (b4 >> 4)];
+}
+
+template <typename T>
+struct AdjState {
+  T toN, toW, toNW, SE;
+};
+
+template <typename T>
+__device__ __forceinline__ void adj_cells4(AdjState<T>& st, const AdjGroup<T>& r, int b4, Vec4<T>& out) {
+  using E = Elem<T>;
+#pragma unroll
+  for (int q = 3; q >= 0; --q) {
+    const uint32_t code = (r.word >> (2 * ((b4 & 15) + q))) & 3u;
+    const T sIn = shl1(st.toN, r.bn.v[q]);       // south: lane r+1 one step back; lane 63: band below
+    const T seNext = shl1(st.toNW, r.bnw.v[q]);  // south-east for the next step
+    T A = E::add(r.gv.v[q], st.SE);
+    A = E::add(A, st.toW);
+    A = E::add(A, sIn);
+    st.toN = code == kSelN ? A : E::zero();
+    st.toW = code == kSelW ? A : E::zero();
+    st.toNW = code == kSelNW ? A : E::zero();
+    st.SE = seNext;
+    out.v[q] = A;
+  }
+}
+
+// Unit u covers slots [S0 - G(u+1), S0 - Gu), groups in descending slot order.
+template <typename T, int G>
+__device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __restrict__ SelR,
+                                         const T* __restrict__ Bn, const T* __restrict__ Bnw, AdjShared& sh,
+                                         Control* ctl, int zero, int u, int Us, int S0, AdjState<T>& st,
+                                         const AdjUnitRegs<T, G>& in, AdjUnitRegs<T, G>& out, uint32_t& stall,
+                                         uint64_t& waited) {
+  using C = BCfg<T>;
+  constexpr int NG = AdjCfg<T, G>::NG, PD = AdjCfg<T, G>::PD;
+  const int lane = threadIdx.x & 63;
+  const int top = S0 - G * u, next_top = top - G;
+  const bool has_next = u + 1 < Us;
+  const uint64_t ready = adj_ready(sh, zero);
+  AdjGroup<T> gr[NG + PD];
+#pragma unroll
+  for (int p = 0; p < PD; ++p) gr[p] = in.g[p];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (g + PD < NG) {
+      adj_load_group<T>(S, SelR, Bn, Bnw, (top - 4 * (g + PD + 1)) & C::MASK, lane, gr[g + PD]);
+    } else if (has_next) {
+      if (g + PD == NG) {
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t need_l = (uint32_t)((G * (u + 1)) / kSub + 1), need_b = (uint32_t)(u + 2);
+        if (!__all((uint32_t)ready >= need_l && (uint32_t)(ready >> 32) >= need_b)) {
+          ++stall;
+          if (!lds_wait_ge(&sh.ctr[0], need_l, &sh.abort, ctl, waited) ||
+              !lds_wait_ge(&sh.ctr[1], need_b, &sh.abort, ctl, waited))
+            return false;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      adj_load_group<T>(S, SelR, Bn, Bnw, (next_top - 4 * (g + PD - NG + 1)) & C::MASK, lane, out.g[g + PD - NG]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const int b4 = (top - 4 * (g + 1)) & C::MASK;
+    Vec4<T> o;
+    adj_cells4<T>(st, gr[g], b4, o);
+    *reinterpret_cast<Vec4<T>*>(S + lane * C::PITCH + b4) = o;
+  }
+  lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
+  __builtin_amdgcn_sched_barrier(0);
+  return true;
+}
+
 template <typename T, int G>
 __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* __restrict__ SelR,
                                             const T* __restrict__ Bn, const T* __restrict__ Bnw, AdjShared& sh,
                                             Control* ctl, int Ks, uint64_t* trace) {
   using C = BCfg<T>;
   using E = typename C::E;
+  constexpr int PD = AdjCfg<T, G>::PD;
   const int lane = threadIdx.x & 63;
   const int S0 = kSub * Ks;  // slots [0, S0), processed from the top down
   const int Us = S0 / G;
-  T toN = E::zero(), toW = E::zero(), toNW = E::zero(), SE = E::zero();
+  AdjState<T> st{E::zero(), E::zero(), E::zero(), E::zero()};
   uint64_t waited = 0, t_first = 0;
   uint32_t stall = 0;
-  uint64_t ready = adj_ready(sh);
-  for (int u = 0; u < Us; ++u) {
-    const uint32_t need_l = (uint32_t)((G * u) / kSub + 1), need_b = (uint32_t)(u + 1);
-    if ((uint32_t)ready < need_l || (uint32_t)(ready >> 32) < need_b) {
+  const int zero = adj_opaque_zero();
+  {
+    const uint64_t ready = adj_ready(sh, zero);
+    if (!__all((uint32_t)ready >= 1u && (uint32_t)(ready >> 32) >= 1u)) {
       ++stall;
-      if (!lds_wait_ge(&sh.ctr[0], need_l, &sh.abort, ctl, waited) ||
-          !lds_wait_ge(&sh.ctr[1], need_b, &sh.abort, ctl, waited)) {
+      if (!lds_wait_ge(&sh.ctr[0], 1u, &sh.abort, ctl, waited) || !lds_wait_ge(&sh.ctr[1], 1u, &sh.abort, ctl, waited)) {
         sh.abort = 1u;
         return;
       }
     }
-    if (trace && u == 0) t_first = __builtin_amdgcn_s_memrealtime();
-    ready = adj_ready(sh);
-    __builtin_amdgcn_sched_barrier(0);
-    const int top = S0 - G * u;  // this unit covers slots [top - G, top)
+  }
+  if (trace) t_first = __builtin_amdgcn_s_memrealtime();
+  AdjUnitRegs<T, G> P, Q;
 #pragma unroll
-    for (int g = 0; g < G / 4; ++g) {
-      const int b4 = (top - 4 * (g + 1)) & C::MASK;
-      const Vec4<T> gv = *reinterpret_cast<const Vec4<T>*>(S + lane * C::PITCH + b4);
-      const Vec4<T> bn = *reinterpret_cast<const Vec4<T>*>(Bn + b4);
-      const Vec4<T> bnw = *reinterpret_cast<const Vec4<T>*>(Bnw + b4);
-      const uint32_t word = SelR[lane * C::SPITCH + (b4 >> 4)];
-      Vec4<T> out;
-#pragma unroll
-      for (int q = 3; q >= 0; --q) {
-        const uint32_t code = (word >> (2 * ((b4 & 15) + q))) & 3u;
-        const T sIn = shl1(toN, bn.v[q]);        // south: lane r+1 one step back; lane 63: band below
-        const T seNext = shl1(toNW, bnw.v[q]);   // south-east for the next step
-        T A = E::add(gv.v[q], SE);
-        A = E::add(A, toW);
-        A = E::add(A, sIn);
-        toN = code == kSelN ? A : E::zero();
-        toW = code == kSelW ? A : E::zero();
-        toNW = code == kSelNW ? A : E::zero();
-        SE = seNext;
-        out.v[q] = A;
-      }
-      *reinterpret_cast<Vec4<T>*>(S + lane * C::PITCH + b4) = out;
+  for (int p = 0; p < PD; ++p) adj_load_group<T>(S, SelR, Bn, Bnw, (S0 - 4 * (p + 1)) & C::MASK, lane, P.g[p]);
+  // Units in pairs, so the next unit's prefetched registers alternate between P and Q.
+  int u = 0;
+  for (; u + 1 < Us; u += 2) {
+    if (!adj_unit<T, G>(S, SelR, Bn, Bnw, sh, ctl, zero, u, Us, S0, st, P, Q, stall, waited) ||
+        !adj_unit<T, G>(S, SelR, Bn, Bnw, sh, ctl, zero, u + 1, Us, S0, st, Q, P, stall, waited)) {
+      sh.abort = 1u;
+      return;
     }
-    lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
-    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (u < Us && !adj_unit<T, G>(S, SelR, Bn, Bnw, sh, ctl, zero, u, Us, S0, st, P, Q, stall, waited)) {
+    sh.abort = 1u;
+    return;
   }
   if (trace && lane == 0) {
     trace[1] = t_first;

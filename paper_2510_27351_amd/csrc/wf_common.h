@@ -46,6 +46,7 @@ struct Elem<float> {
   __device__ static __forceinline__ float min3(float a, float b, float c) {
     return __builtin_fminf(__builtin_fminf(a, b), c);
   }
+  __device__ static __forceinline__ float min2(float a, float b) { return __builtin_fminf(a, b); }
   __device__ static __forceinline__ float add(float c, float v) { return c + v; }
   __device__ static __forceinline__ uint32_t word(float x, int) { return __builtin_bit_cast(uint32_t, x); }
   __device__ static __forceinline__ float from_words(const uint32_t* w) { return __builtin_bit_cast(float, w[0]); }
@@ -66,6 +67,7 @@ struct Elem<int32_t> {
     int32_t x = a < b ? a : b;
     return x < c ? x : c;
   }
+  __device__ static __forceinline__ int32_t min2(int32_t a, int32_t b) { return a < b ? a : b; }
   // Saturating, so that +inf (INT32_MAX) stays +inf on the virtual border; real cells
   // never saturate under the documented bound on |C|.
   __device__ static __forceinline__ int32_t add(int32_t c, int32_t v) { return __builtin_elementwise_add_sat(c, v); }
@@ -94,6 +96,7 @@ struct Elem<double> {
   __device__ static __forceinline__ double min3(double a, double b, double c) {
     return __builtin_fmin(__builtin_fmin(a, b), c);
   }
+  __device__ static __forceinline__ double min2(double a, double b) { return __builtin_fmin(a, b); }
   __device__ static __forceinline__ double add(double c, double v) { return c + v; }
   __device__ static __forceinline__ uint32_t word(double x, int k) {
     uint64_t b = __builtin_bit_cast(uint64_t, x);
