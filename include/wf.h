@@ -83,7 +83,7 @@ int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k);
  * score are the forward results for C.  The derivative is the routed (sub)gradient of the
  * min: each cell passes its adjoint to the one predecessor it selected (ties NW, N, W), so
  * A[i][j] = g_D[i][j] + [i=m-1, j=n-1] g_score + [SEL(i+1,j+1)=NW] A[i+1][j+1]
- *         + [SEL(i,j+1)=W] A[i][j+1] + [SEL(i+1,j)=N] A[i+1][j]   (summed in that order)
+ *         + [SEL(i+1,j)=N] A[i+1][j] + [SEL(i,j+1)=W] A[i][j+1]   (summed in that order)
  * and g_C = A.  The selections are recomputed on the device from the input and either the
  * checkpoint grid of wf_forward (its band rows; pass ckpt_k > 0 and D = NULL) or the saved
  * table D (pass ckpt = NULL, ckpt_k = 0).
@@ -95,9 +95,9 @@ int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k);
  *   g_score     one element, or NULL for 0.
  *   g_D, ldgd   m x n upstream gradient of the table, or NULL for 0.
  *   g_C, ldgc   m x n output.
- * Uses (and grows) the device workspace: 2 bits per cell for the selections plus handoff
- * words.  Results are bitwise reproducible; in float the sums round once per term in the
- * order above.
+ * Uses (and grows) the device workspace: 4 bits per cell for the selections (three bit-planes
+ * and padding) plus handoff words.  Results are bitwise reproducible; in float the sums
+ * round once per term in the order above.
  */
 int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt,
                 int32_t ckpt_k, const void* D, int64_t ldd, const void* g_score, const void* g_D,

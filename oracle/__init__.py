@@ -58,7 +58,7 @@ def _load():
     lib.wfo_backward_f32.argtypes = [i64, i64, p, p, i64, ctypes.c_float, p, i64]
     lib.wfo_backward_f32.restype = None
     lib.wfo_version.restype = ctypes.c_int
-    if lib.wfo_version() != 1:
+    if lib.wfo_version() != 2:
         raise RuntimeError("stale oracle build")
     _lib = lib
     return lib

@@ -21,11 +21,12 @@
  *   (sub)gradient A = dL/dD = dL/dC is, in reverse row-major order,
  *       A[i][j] = gD[i][j] + [i==m-1 && j==n-1] * gscore
  *               + [SEL[i+1][j+1] == NW] * A[i+1][j+1]
- *               + [SEL[i][j+1]   == W ] * A[i][j+1]
  *               + [SEL[i+1][j]   == N ] * A[i+1][j]
+ *               + [SEL[i][j+1]   == W ] * A[i][j+1]
  *   summed left to right in exactly that order, and gC = A.  (The order of the three
- *   routed terms is a reading: the paper gives none.  This one adds the term known
- *   earliest in a reverse anti-diagonal sweep first.)
+ *   routed terms is a reading: the paper gives none.  This one adds the terms that come
+ *   from the row below first and the term from the same row last, so that in a sweep by
+ *   row bands every contribution from the band below is known before the row's own.)
  *
  * Precision: the f64 forms accumulate in double (inputs may be float data widened to
  * double, so input quantisation is not counted as error); the f32 forms perform exactly one
@@ -104,8 +105,8 @@ void wfo_forward_i64(int64_t m, int64_t n, const int64_t* C, int64_t ldc, int64_
         if (i == m - 1 && j == n - 1) a = a + gscore;                                      \
         if (i + 1 < m && j + 1 < n && sel[(i + 1) * n + (j + 1)] == WFO_SEL_NW)            \
           a = a + gC[(i + 1) * ldgc + (j + 1)];                                            \
-        if (j + 1 < n && sel[i * n + (j + 1)] == WFO_SEL_W) a = a + gC[i * ldgc + (j + 1)]; \
         if (i + 1 < m && sel[(i + 1) * n + j] == WFO_SEL_N) a = a + gC[(i + 1) * ldgc + j]; \
+        if (j + 1 < n && sel[i * n + (j + 1)] == WFO_SEL_W) a = a + gC[i * ldgc + (j + 1)]; \
         gC[i * ldgc + j] = a;                                                              \
       }                                                                                    \
     }                                                                                      \
@@ -115,4 +116,4 @@ WFO_DEFINE_BACKWARD(wfo_backward_f64, double)
 WFO_DEFINE_BACKWARD(wfo_backward_f32, float)
 
 /* Version tag so the Python wrapper can refuse a stale build. */
-int wfo_version(void) { return 1; }
+int wfo_version(void) { return 2; }

@@ -208,7 +208,7 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   DeviceWs* ws = nullptr;
   int rc = ensure_ws(dev, words, &ws);
   if (rc != WF_OK) return rc;
-  rc = ensure_sel(ws, (size_t)nb * (size_t)Ks * 64 * 4);
+  rc = ensure_sel(ws, (size_t)nb * (size_t)Ks * 64 * 8);
   if (rc != WF_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int grid = (int)std::min<int64_t>(nb, ws->num_cus);

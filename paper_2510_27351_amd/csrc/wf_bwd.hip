@@ -2,27 +2,31 @@
 //
 // The routed adjoint of  L = sum(gD * D) + gscore * score  is
 //     A[i][j] = gD[i][j] + [last] gscore + [SEL(i+1,j+1) = NW] A[i+1][j+1]
-//             + [SEL(i,j+1) = W] A[i][j+1] + [SEL(i+1,j) = N] A[i+1][j],       gC = A,
-// summed in exactly that order (reading R0; the paper states no recurrence).  SEL(i,j) is the
-// predecessor cell (i,j) took in the forward min, ties broken NW, N, W.
+//             + [SEL(i+1,j) = N] A[i+1][j] + [SEL(i,j+1) = W] A[i][j+1],       gC = A,
+// summed in exactly that order (reading R0; the paper states no recurrence and no order for
+// the routed terms: the two from the row below come first, the one from the same row last).
+// SEL(i,j) is the predecessor cell (i,j) took in the forward min, ties broken NW, N, W.
 //
 // Two launches:
 //  1. Selection recompute.  Every 64-row band is swept again left to right from its top
 //     row, which the forward pass stored as a checkpoint row (or which the caller's saved
 //     table provides).  The bands are therefore independent and all run at once.  The
-//     sweep is the forward cell chain plus the two comparisons that name the predecessor;
-//     it emits 2-bit codes, 16 per 32-bit word per lane.
+//     sweep is the forward cell chain plus the comparisons that name the predecessor; it
+//     emits three bit-planes per row (selected W, selected N, selected NW), one bit per
+//     cell.
 //  2. Reverse sweep.  Bands from the bottom up, each a skewed wavefront from right to left:
 //     lane r owns band row r and at reverse step t handles slot s = S - t (slot = row +
-//     column), so lane r+1 handles a column one step before lane r does.  A cell's three
-//     inputs are the routed values its successors pushed: from the south (lane r+1, one step
-//     back, DPP wave_shl:1), from the east (the lane itself, one step back) and from the
-//     south-east (lane r+1, two steps back).  Lane 63 takes the south and south-east values
-//     from the band below, which publishes them (tagged 64-bit words, as in the forward
-//     sweep).  After computing A a cell pushes it to the predecessor its code names and zero
-//     to the others.
-// Waves of the reverse sweep: compute; loader (gD and the selection words into LDS);
-// poller (values from the band below); storer (gC); publisher (values for the band above).
+//     column), so lane r+1 handles a column one step before lane r does.  A cell's routed
+//     inputs come from the south-east (lane r+1, two steps back), the south (lane r+1, one
+//     step back) and the east (the lane itself, one step back); each is the successor's A
+//     times a 0/1 factor (did that successor select this cell?), so every term is one
+//     fused multiply-add, and the lane-shifted ones take their operand through DPP
+//     wave_shl:1.  The loader turns the bit-planes into those factors, already aligned to
+//     the receiving cell, as bytes in LDS.  Lane 63's inputs come from the band below, which
+//     publishes them (tagged 64-bit words, as in the forward sweep); the poller adds them to
+//     lane 63's upstream value before the compute wave reads it.
+// Waves of the reverse sweep: compute; loader (gD, factors); poller (values from the band
+// below); storer (gC); publisher (values for the band above).
 #include "wf_common.h"
 
 namespace wf {
@@ -53,20 +57,24 @@ __device__ __forceinline__ T shl1(T src, T old) {
   }
 }
 
+// LDS rings of the adjoint kernels: RING slots per row.  The value ring's row pitch is 16 mod
+// 256 bytes (conflict-free 16-byte accesses of 64 rows); the factor ring holds one word per
+// slot (4 one-byte factors per 4-slot group and word) with the same property.
 template <typename T>
 struct BCfg {
   using E = Elem<T>;
-  static constexpr int RING = E::RING;
-  static constexpr int PITCH = E::PITCH;
+  static constexpr int RING = sizeof(T) == 4 ? 256 : 128;
+  static constexpr int PITCH = RING + 16 / (int)sizeof(T);
+  static constexpr int FPITCH = RING + 4;
   static constexpr int MASK = RING - 1;
-  static constexpr int SW = RING / 16;   // selection words per lane in the ring
-  static constexpr int SPITCH = SW + 4;  // their row pitch (16-byte aligned rows)
+  static constexpr int NSUB = RING / kSub;  // 64-slot sub-chunks in a ring
 };
 
-// Layout of the selection words in global memory: for band b, sub-chunk k (slots
-// [64k, 64k+64)), lane r, the four words covering those slots are contiguous.
+// Layout of the selection bit-planes in global memory: for band b, sub-chunk k (slots
+// [64k, 64k+64)) and lane r, eight words: W[0..1], N[0..1], NW[0..1], 0, 0 -- bit j of word
+// h of a plane is slot 64k + 32h + j of row r.
 __device__ __forceinline__ int64_t sel_index(int band, int Ks, int k, int lane) {
-  return (((int64_t)band * Ks + k) * 64 + lane) * 4;
+  return (((int64_t)band * Ks + k) * 64 + lane) * 8;
 }
 
 // =======================================================================================
@@ -84,6 +92,7 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
                                             const SelArgs& a, int band, int Ks) {
   using C = BCfg<T>;
   using E = typename C::E;
+  typedef int v4i __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
   const int64_t n = opaque(a.n);
   const int rows = (int)(a.m - (int64_t)band * kBand < kBand ? a.m - (int64_t)band * kBand : kBand);
@@ -97,44 +106,54 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
       return;
     }
     const int base = (kSub * k) & C::MASK;
-    uint32_t words[4];
+    uint32_t pl[3][2];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      uint32_t word = 0;
+    for (int h = 0; h < 2; ++h) {
+      // planes, first step in the most significant bit
+      uint32_t pw = 0, pn = 0, pnw = 0;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int off = base + 16 * w + 4 * g;
+      for (int g = 0; g < 8; ++g) {
+        const int off = base + 32 * h + 4 * g;
         const Vec4<T> cv = *reinterpret_cast<const Vec4<T>*>(S + lane * C::PITCH + off);
         const Vec4<T> tv = *reinterpret_cast<const Vec4<T>*>(Tr + off);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const T N = E::shr1(X, tv.v[q]);
-          // predecessor code with ties to NW, then N, then W (strict comparisons)
+          // predecessor: NW unless N is strictly smaller; W if strictly smaller than both
           const bool n_lt = N < NW;
-          const T m1 = n_lt ? N : NW;
-          const bool w_lt = X < m1;
-          const uint32_t code = w_lt ? kSelW : (n_lt ? kSelN : kSelNW);
-          word |= code << (2 * (4 * g + q));
-          X = E::add(cv.v[q], w_lt ? X : m1);
+          const bool w_lt = X < E::min2(NW, N);
+          pw = (pw << 1) | (uint32_t)w_lt;
+          pn = (pn << 1) | (uint32_t)(n_lt && !w_lt);
+          pnw = (pnw << 1) | (uint32_t)(!n_lt && !w_lt);
+          X = E::add(cv.v[q], E::min3(NW, N, X));
           NW = N;
         }
       }
-      // zero the codes of cells outside the matrix (and of cell (0,0), which has none)
-      const int t0 = kSub * k + 16 * w;
-      if (!(rows == kBand && t0 >= kBand - 1 && (int64_t)t0 + 16 <= n)) {
+      pw = __builtin_bitreverse32(pw);
+      pn = __builtin_bitreverse32(pn);
+      pnw = __builtin_bitreverse32(pnw);
+      // clear the bits of cells outside the matrix (and of cell (0,0), which selects nothing)
+      const int t0 = kSub * k + 32 * h;
+      if (!(rows == kBand && t0 >= kBand - 1 && (int64_t)t0 + 32 <= n)) {
         const int64_t lo = lane - (int64_t)t0, hi = n + lane - (int64_t)t0;  // valid steps [lo, hi)
-        const int a0 = (int)(lo < 0 ? 0 : (lo > 16 ? 16 : lo));
-        const int a1 = (int)(hi < 0 ? 0 : (hi > 16 ? 16 : hi));
-        uint64_t msk = a1 > a0 ? (((uint64_t)1 << (2 * a1)) - 1) & ~(((uint64_t)1 << (2 * a0)) - 1) : 0;
+        const int a0 = (int)(lo < 0 ? 0 : (lo > 32 ? 32 : lo));
+        const int a1 = (int)(hi < 0 ? 0 : (hi > 32 ? 32 : hi));
+        uint64_t msk = a1 > a0 ? (((uint64_t)1 << a1) - 1) & ~(((uint64_t)1 << a0) - 1) : 0;
         if (lane >= rows) msk = 0;
-        if (band == 0 && lane == 0 && t0 == 0) msk &= ~(uint64_t)3;
-        word &= (uint32_t)msk;
+        if (band == 0 && lane == 0 && t0 == 0) msk &= ~(uint64_t)1;
+        pw &= (uint32_t)msk;
+        pn &= (uint32_t)msk;
+        pnw &= (uint32_t)msk;
       }
-      words[w] = word;
+      pl[0][h] = pw;
+      pl[1][h] = pn;
+      pl[2][h] = pnw;
     }
-    typedef int v4i __attribute__((ext_vector_type(4)));
-    const v4i wv = {(int)words[0], (int)words[1], (int)words[2], (int)words[3]};
-    __builtin_nontemporal_store(wv, reinterpret_cast<v4i*>(out + sel_index(band, Ks, k, lane)));
+    const v4i w0 = {(int)pl[0][0], (int)pl[0][1], (int)pl[1][0], (int)pl[1][1]};
+    const v4i w1 = {(int)pl[2][0], (int)pl[2][1], 0, 0};
+    v4i* dst = reinterpret_cast<v4i*>(out + sel_index(band, Ks, k, lane));
+    __builtin_nontemporal_store(w0, dst);
+    __builtin_nontemporal_store(w1, dst + 1);
     lds_signal(&sh.steps, (uint32_t)(kSub * (k + 1)));
   }
 }
@@ -151,6 +170,8 @@ struct SelPF {
 template <typename T>
 __device__ __forceinline__ void sel_load_sub(Vec4<T> (&x)[16], T& tv, __amdgpu_buffer_rsrc_t rsrc, int64_t ldc,
                                              const T* top, int64_t n, int k) {
+  // Every call issues the same loads (no branch around any of them), so the compiler can
+  // count the loads in flight and wait for the oldest sub-chunk only.
   const int lane = threadIdx.x & 63;
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -168,13 +189,13 @@ __device__ __forceinline__ void sel_load_sub(Vec4<T> (&x)[16], T& tv, __amdgpu_b
     }
   }
   const int64_t j = (int64_t)kSub * k + lane;
-  tv = (top && j < n) ? top[j] : Elem<T>::inf();
+  tv = top[j < n ? j : n - 1];  // replaced by +inf in sel_store_sub where not a real column
   __builtin_amdgcn_sched_barrier(0);
 }
 
 template <typename T>
-__device__ __forceinline__ void sel_store_sub(T* S, T* Tr, const Vec4<T> (&x)[16], T tv, int k, int rows,
-                                              int64_t n) {
+__device__ __forceinline__ void sel_store_sub(T* S, T* Tr, const Vec4<T> (&x)[16], T tv, bool has_top, int k,
+                                              int rows, int64_t n) {
   using C = BCfg<T>;
   using E = typename C::E;
   const int lane = threadIdx.x & 63;
@@ -191,7 +212,8 @@ __device__ __forceinline__ void sel_store_sub(T* S, T* Tr, const Vec4<T> (&x)[16
     }
     *reinterpret_cast<Vec4<T>*>(S + i * C::PITCH + ((kSub * k + 4 * (lane & 15)) & C::MASK)) = y;
   }
-  Tr[(kSub * k + lane) & C::MASK] = tv;
+  const int64_t j = (int64_t)kSub * k + lane;
+  Tr[(kSub * k + lane) & C::MASK] = (has_top && j < n) ? tv : E::inf();
 }
 
 template <typename T>
@@ -205,30 +227,42 @@ __device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const Sel
   // from the range-checked buffer; sel_store_sub replaces them by +inf.
   const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(static_cast<const T*>(a.C) + row0 * ldc,
                                                 (uint32_t)(((rows - 1) * ldc + n) * (int64_t)sizeof(T)));
-  const T* top = band > 0 ? static_cast<const T*>(a.top) + (int64_t)(band - 1) * a.ld_top : nullptr;
+  // the first band has no row above: its loads read row 0 of C and are replaced by +inf
+  const bool has_top = band > 0;
+  const T* top = has_top ? static_cast<const T*>(a.top) + (int64_t)(band - 1) * a.ld_top : static_cast<const T*>(a.C);
   uint64_t waited = 0;
   Vec4<T> buf[PF][16];
   T tv[PF];
+  // The loads of sub-chunk k+PF are issued right after sub-chunk k is stored, unconditionally
+  // (clamped to the last sub-chunk), so that PF sub-chunks are in flight at every wait.
 #pragma unroll
-  for (int p = 0; p < PF; ++p)
-    if (p < Ks) sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, p);
-  for (int k0 = 0; k0 < Ks; k0 += PF) {
+  for (int p = 0; p < PF; ++p) sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, p < Ks ? p : Ks - 1);
+  auto store = [&](int p, int k) -> bool {
+    // sub-chunk k reuses the ring slots of sub-chunk k - RING/64
+    const int older = k - C::RING / kSub;
+    if (older >= 0 &&
+        !lds_wait_ge<false>(&sh.steps, (uint32_t)(kSub * (older + 1)), &sh.abort, a.ctl, waited)) {
+      sh.abort = 1u;
+      return false;
+    }
+    sel_store_sub<T>(S, Tr, buf[p], tv[p], has_top, k, rows, n);
+    lds_publish(&sh.loaded, (uint32_t)(k + 1));
+    return true;
+  };
+  // Whole groups of PF sub-chunks carry no condition around the stores, which keeps the
+  // compiler's wait counts at PF - 1 sub-chunks in flight; the last partial group follows.
+  int k0 = 0;
+  for (; k0 + PF <= Ks; k0 += PF) {
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
       const int k = k0 + p;
-      if (k >= Ks) break;
-      // sub-chunk k reuses the ring slots of sub-chunk k - RING/64
-      const int older = k - C::RING / kSub;
-      if (older >= 0 &&
-          !lds_wait_ge<false>(&sh.steps, (uint32_t)(kSub * (older + 1)), &sh.abort, a.ctl, waited)) {
-        sh.abort = 1u;
-        return;
-      }
-      sel_store_sub<T>(S, Tr, buf[p], tv[p], k, rows, n);
-      lds_publish(&sh.loaded, (uint32_t)(k + 1));
-      if (k + PF < Ks) sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, k + PF);
+      if (!store(p, k)) return;
+      sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, k + PF < Ks ? k + PF : Ks - 1);
     }
   }
+#pragma unroll
+  for (int p = 0; p < PF; ++p)
+    if (k0 + p < Ks && !store(p, k0 + p)) return;
 }
 
 template <typename T>
@@ -264,8 +298,9 @@ __global__ __launch_bounds__(128, 1) void sel_kernel(SelArgs a) {
 // 2. Reverse sweep: five waves, one 64-row band per workgroup, bands from the bottom up.
 // =======================================================================================
 struct alignas(8) AdjShared {
-  uint32_t ctr[6];  // 0: sub-chunks loaded (gD + selection), 1: bottom units loaded,
-                    // 2: reverse steps done, 3: sub-chunks stored, 4: units published
+  uint32_t ctr[6];  // 0: sub-chunks loaded (upstream values + factors), 1: units whose lane-63
+                    // inputs from the band below are added in, 2: reverse steps done,
+                    // 3: sub-chunks stored, 4: units published
   uint32_t item;
   uint32_t abort;
 };
@@ -284,14 +319,36 @@ __device__ __forceinline__ int adj_opaque_zero() {
   return z;
 }
 
+// wave_shl:1 with bound_ctrl: lane r receives lane r+1's value, lane 63 reads zero.  Feeding
+// a multiply or a fused multiply-add, the move folds into a DPP form of that instruction.
+template <typename T>
+__device__ __forceinline__ T shl1z(T src) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, src), 0x130, 0xf, 0xf, true));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x130, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+__device__ __forceinline__ uint32_t shl1z_u32(uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)src, 0x130, 0xf, 0xf, true);
+}
+
+// 0/1 factor held in byte q of a factor word, as an element value (one v_cvt_f32_ubyteN).
+template <typename T, int q>
+__device__ __forceinline__ T factor(uint32_t w) {
+  return (T)(float)((w >> (8 * q)) & 0xFFu);
+}
+
 // wave 0: the reverse chain.  Slot group [b4, b4+4) is processed from b4+3 down to b4.
-// The LDS reads of a group (the upstream values, the band-below values and the selection
-// word) are issued PD groups ahead of their use: LDS latency under the other waves'
-// traffic is longer than one group's compute.
+// The LDS reads of a group (upstream values and factor words) are issued PD groups ahead of
+// their use: LDS latency under the other waves' traffic is longer than one group's compute.
 template <typename T>
 struct AdjGroup {
-  Vec4<T> gv, bn, bnw;
-  uint32_t word;
+  Vec4<T> gv;      // upstream value gD (+ gscore; lane 63: + the band below's inputs)
+  uint32_t f[3];   // factor words: [0] W (east), [1] N (south), [2] NW (south-east)
 };
 
 template <typename T, int G>
@@ -306,44 +363,51 @@ struct AdjUnitRegs {
 };
 
 template <typename T>
-__device__ __forceinline__ void adj_load_group(const T* __restrict__ S, const uint32_t* __restrict__ SelR,
-                                               const T* __restrict__ Bn, const T* __restrict__ Bnw, int b4, int lane,
-                                               AdjGroup<T>& r) {
+__device__ __forceinline__ void adj_load_group(const T* __restrict__ S, const uint32_t* __restrict__ F, int b4,
+                                               int lane, AdjGroup<T>& r) {
   using C = BCfg<T>;
   r.gv = *reinterpret_cast<const Vec4<T>*>(S + lane * C::PITCH + b4);
-  r.bn = *reinterpret_cast<const Vec4<T>*>(Bn + b4);
-  r.bnw = *reinterpret_cast<const Vec4<T>*>(Bnw + b4);
-  r.word = SelR[lane * C::SPITCH + (b4 >> 4)];
+  // three words: a read of the unused fourth would leave a register that the compiler
+  // reuses as a temporary while the read is still in flight
+  typedef uint32_t v3u __attribute__((ext_vector_type(3)));
+  const v3u f = *reinterpret_cast<const v3u*>(F + lane * C::FPITCH + b4);
+  r.f[0] = f.x;
+  r.f[1] = f.y;
+  r.f[2] = f.z;
 }
 
 template <typename T>
 struct AdjState {
-  T toN, toW, toNW, SE;
+  T A1;  // A of the previous step (slot + 1)
+  T A2;  // A two steps back (slot + 2)
 };
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T, int q>
+__device__ __forceinline__ T adj_cell(AdjState<T>& st, const AdjGroup<T>& r) {
+  // ((gv + NW-routed) + N-routed) + W-routed, one rounding per term: a factor is 0 or 1,
+  // so each product is exact and each fused multiply-add rounds once.
+  const T p = fma_t(shl1z(st.A2), factor<T, q>(r.f[2]), r.gv.v[q]);
+  const T s = fma_t(shl1z(st.A1), factor<T, q>(r.f[1]), p);
+  const T A = fma_t(st.A1, factor<T, q>(r.f[0]), s);
+  st.A2 = st.A1;
+  st.A1 = A;
+  return A;
+}
+
 template <typename T>
-__device__ __forceinline__ void adj_cells4(AdjState<T>& st, const AdjGroup<T>& r, int b4, Vec4<T>& out) {
-  using E = Elem<T>;
-#pragma unroll
-  for (int q = 3; q >= 0; --q) {
-    const uint32_t code = (r.word >> (2 * ((b4 & 15) + q))) & 3u;
-    const T sIn = shl1(st.toN, r.bn.v[q]);       // south: lane r+1 one step back; lane 63: band below
-    const T seNext = shl1(st.toNW, r.bnw.v[q]);  // south-east for the next step
-    T A = E::add(r.gv.v[q], st.SE);
-    A = E::add(A, st.toW);
-    A = E::add(A, sIn);
-    st.toN = code == kSelN ? A : E::zero();
-    st.toW = code == kSelW ? A : E::zero();
-    st.toNW = code == kSelNW ? A : E::zero();
-    st.SE = seNext;
-    out.v[q] = A;
-  }
+__device__ __forceinline__ void adj_cells4(AdjState<T>& st, const AdjGroup<T>& r, Vec4<T>& out) {
+  out.v[3] = adj_cell<T, 3>(st, r);
+  out.v[2] = adj_cell<T, 2>(st, r);
+  out.v[1] = adj_cell<T, 1>(st, r);
+  out.v[0] = adj_cell<T, 0>(st, r);
 }
 
 // Unit u covers slots [S0 - G(u+1), S0 - Gu), groups in descending slot order.
 template <typename T, int G>
-__device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __restrict__ SelR,
-                                         const T* __restrict__ Bn, const T* __restrict__ Bnw, AdjShared& sh,
+__device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __restrict__ F, AdjShared& sh,
                                          Control* ctl, int zero, int u, int Us, int S0, AdjState<T>& st,
                                          const AdjUnitRegs<T, G>& in, AdjUnitRegs<T, G>& out, uint32_t& stall,
                                          uint64_t& waited) {
@@ -359,7 +423,7 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (g + PD < NG) {
-      adj_load_group<T>(S, SelR, Bn, Bnw, (top - 4 * (g + PD + 1)) & C::MASK, lane, gr[g + PD]);
+      adj_load_group<T>(S, F, (top - 4 * (g + PD + 1)) & C::MASK, lane, gr[g + PD]);
     } else if (has_next) {
       if (g + PD == NG) {
         __builtin_amdgcn_sched_barrier(0);
@@ -372,12 +436,12 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      adj_load_group<T>(S, SelR, Bn, Bnw, (next_top - 4 * (g + PD - NG + 1)) & C::MASK, lane, out.g[g + PD - NG]);
+      adj_load_group<T>(S, F, (next_top - 4 * (g + PD - NG + 1)) & C::MASK, lane, out.g[g + PD - NG]);
     }
     __builtin_amdgcn_sched_barrier(0);
     const int b4 = (top - 4 * (g + 1)) & C::MASK;
     Vec4<T> o;
-    adj_cells4<T>(st, gr[g], b4, o);
+    adj_cells4<T>(st, gr[g], o);
     *reinterpret_cast<Vec4<T>*>(S + lane * C::PITCH + b4) = o;
   }
   lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
@@ -386,8 +450,7 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
 }
 
 template <typename T, int G>
-__device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* __restrict__ SelR,
-                                            const T* __restrict__ Bn, const T* __restrict__ Bnw, AdjShared& sh,
+__device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* __restrict__ F, AdjShared& sh,
                                             Control* ctl, int Ks, uint64_t* trace) {
   using C = BCfg<T>;
   using E = typename C::E;
@@ -395,7 +458,7 @@ __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* _
   const int lane = threadIdx.x & 63;
   const int S0 = kSub * Ks;  // slots [0, S0), processed from the top down
   const int Us = S0 / G;
-  AdjState<T> st{E::zero(), E::zero(), E::zero(), E::zero()};
+  AdjState<T> st{E::zero(), E::zero()};
   uint64_t waited = 0, t_first = 0;
   uint32_t stall = 0;
   const int zero = adj_opaque_zero();
@@ -412,17 +475,17 @@ __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* _
   if (trace) t_first = __builtin_amdgcn_s_memrealtime();
   AdjUnitRegs<T, G> P, Q;
 #pragma unroll
-  for (int p = 0; p < PD; ++p) adj_load_group<T>(S, SelR, Bn, Bnw, (S0 - 4 * (p + 1)) & C::MASK, lane, P.g[p]);
+  for (int p = 0; p < PD; ++p) adj_load_group<T>(S, F, (S0 - 4 * (p + 1)) & C::MASK, lane, P.g[p]);
   // Units in pairs, so the next unit's prefetched registers alternate between P and Q.
   int u = 0;
   for (; u + 1 < Us; u += 2) {
-    if (!adj_unit<T, G>(S, SelR, Bn, Bnw, sh, ctl, zero, u, Us, S0, st, P, Q, stall, waited) ||
-        !adj_unit<T, G>(S, SelR, Bn, Bnw, sh, ctl, zero, u + 1, Us, S0, st, Q, P, stall, waited)) {
+    if (!adj_unit<T, G>(S, F, sh, ctl, zero, u, Us, S0, st, P, Q, stall, waited) ||
+        !adj_unit<T, G>(S, F, sh, ctl, zero, u + 1, Us, S0, st, Q, P, stall, waited)) {
       sh.abort = 1u;
       return;
     }
   }
-  if (u < Us && !adj_unit<T, G>(S, SelR, Bn, Bnw, sh, ctl, zero, u, Us, S0, st, P, Q, stall, waited)) {
+  if (u < Us && !adj_unit<T, G>(S, F, sh, ctl, zero, u, Us, S0, st, P, Q, stall, waited)) {
     sh.abort = 1u;
     return;
   }
@@ -434,13 +497,19 @@ __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* _
   }
 }
 
-// wave 1: loader of gD (plus gscore on the last cell; zeros when gD is absent) and of the
-// selection words, one 64-slot sub-chunk at a time from the top slot down.  The loads of
-// the next PF sub-chunks are in flight in registers while one is written to LDS.
+// wave 1: loader, one 64-slot sub-chunk at a time from the top slot down:
+//  - upstream values gD (plus gscore on the last cell; zeros when gD is absent) into the
+//    value ring;
+//  - the factor words: for the cell of lane r at slot s, byte 0 of the W word says whether
+//    cell (r, slot s+1) selected W, byte 0 of the N word whether (r+1, s+1) selected N, byte
+//    0 of the NW word whether (r+1, s+2) selected NW -- i.e. whether that successor routes
+//    its value here -- and bytes 1..3 the same for slots s+1..s+3 (the group of 4 slots);
+//  - row 0's own N and NW planes, which the publisher needs.
+// The loads of the next PF (gD) and PFS (planes) sub-chunks are in flight in registers.
 template <typename T>
 struct AdjPF {
   static constexpr int PF = 1;                         // gD sub-chunks
-  static constexpr int PFS = 4;                        // selection-word sub-chunks
+  static constexpr int PFS = 4;                        // bit-plane sub-chunks
 };
 
 template <typename T>
@@ -468,8 +537,15 @@ __device__ __forceinline__ void adj_load_g(Vec4<T> (&x)[16], __amdgpu_buffer_rsr
 
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 
+// The four 0/1 bits of a 64-bit plane at slots [4g, 4g+4), spread to the four bytes of a word.
+__device__ __forceinline__ uint32_t spread4(uint64_t bits, int g) {
+  const uint32_t nib = (uint32_t)(bits >> (4 * g)) & 0xFu;
+  return (nib * 0x00204081u) & 0x01010101u;
+}
+
 template <typename T, int G>
-__device__ __forceinline__ void adj_loader(T* S, uint32_t* SelR, AdjShared& sh, const AdjArgs& a, int band, int Ks) {
+__device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, AdjShared& sh, const AdjArgs& a,
+                                           int band, int Ks) {
   using C = BCfg<T>;
   using E = typename C::E;
   constexpr int PF = AdjPF<T>::PF, PFS = AdjPF<T>::PFS;
@@ -478,43 +554,51 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* SelR, AdjShared& sh, 
   const int64_t ldg = opaque(a.ldgd), n = opaque(a.n), m = opaque(a.m);
   const int64_t row0 = (int64_t)band * kBand;
   const int rows = (int)(m - row0 < kBand ? m - row0 : kBand);
+  // Without gD the buffer covers no bytes: the loads still issue (so that every sub-chunk
+  // has the same loads in flight and the compiler can wait for the oldest only) and return
+  // zeros.
   const bool has_g = a.gD != nullptr;
   const __amdgpu_buffer_rsrc_t rsrc =
-      make_rsrc(has_g ? static_cast<const T*>(a.gD) + row0 * ldg : nullptr,
+      make_rsrc(has_g ? static_cast<const T*>(a.gD) + row0 * ldg : a.gC,
                 has_g ? (uint32_t)(((rows - 1) * ldg + n) * (int64_t)sizeof(T)) : 0u);
   // gscore lands on cell (m-1, n-1): band row m-1-row0, slot n-1 + that row
   const int64_t last_row = m - 1 - row0;
   const bool has_last = last_row >= 0 && last_row < kBand && a.gscore != nullptr;
   const T gs = has_last ? *static_cast<const T*>(a.gscore) : E::zero();
   const int64_t last_slot = n - 1 + last_row;
-  const uint32_t* selp = a.sel + sel_index(band, Ks, 0, lane);  // + 256 words per sub-chunk
+  const uint32_t* selp = a.sel + sel_index(band, Ks, 0, lane);  // + 512 words per sub-chunk
   uint64_t waited = 0;
   Vec4<T> gbuf[PF][16];
-  v4i_t sbuf[PFS];
+  v4i_t sbuf[PFS][2];
+  // bits of the slots just above the current sub-chunk (the one processed before it)
+  uint64_t carry_w = 0, carry_n = 0, carry_nw = 0;
   // reverse order: the kr-th sub-chunk processed is k = Ks-1-kr
+  // Loads are issued unconditionally (indices clamped to sub-chunk 0), PFS / PF sub-chunks
+  // ahead, so that the number in flight is the same at every wait.
 #pragma unroll
-  for (int p = 0; p < PFS; ++p)
-    if (p < Ks) sbuf[p] = __builtin_nontemporal_load(reinterpret_cast<const v4i_t*>(selp + (int64_t)(Ks - 1 - p) * 256));
-  if (has_g) {
-#pragma unroll
-    for (int p = 0; p < PF; ++p)
-      if (p < Ks) adj_load_g<T>(gbuf[p], rsrc, ldg, Ks - 1 - p);
+  for (int p = 0; p < PFS; ++p) {
+    const v4i_t* src = reinterpret_cast<const v4i_t*>(selp + (int64_t)(Ks - 1 - p >= 0 ? Ks - 1 - p : 0) * 512);
+    sbuf[p][0] = __builtin_nontemporal_load(src);
+    sbuf[p][1] = __builtin_nontemporal_load(src + 1);
   }
+#pragma unroll
+  for (int p = 0; p < PF; ++p) adj_load_g<T>(gbuf[p], rsrc, ldg, Ks - 1 - p >= 0 ? Ks - 1 - p : 0);
   for (int kr0 = 0; kr0 < Ks; kr0 += PFS) {
 #pragma unroll
     for (int p = 0; p < PFS; ++p) {
       const int kr = kr0 + p;
-      if (kr >= Ks) break;
       const int k = Ks - 1 - kr;  // sub-chunk (slots [64k, 64k+64))
-      const int older = kr - C::RING / kSub;
+      Vec4<T>(&gx)[16] = gbuf[p % PF];
+      if (kr < Ks) {
+      const int older = kr - C::NSUB;
       if (older >= 0 && (!lds_wait_ge<false>(&sh.ctr[3], (uint32_t)(older + 1), &sh.abort, a.ctl, waited) ||
                          !lds_wait_ge<false>(&sh.ctr[4], (uint32_t)((kSub / G) * (older + 1)), &sh.abort, a.ctl,
                                              waited))) {
         sh.abort = 1u;
         return;
       }
+      // upstream values
       const bool interior = rows == kBand && k > 0 && (int64_t)kSub * k + kSub <= n;
-      Vec4<T>(&gx)[16] = gbuf[p % PF];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int i = 4 * v + (lane >> 4);
@@ -539,85 +623,121 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* SelR, AdjShared& sh, 
         }
         *reinterpret_cast<Vec4<T>*>(S + i * C::PITCH + (slot & C::MASK)) = x;
       }
-      *reinterpret_cast<v4i_t*>(SelR + lane * C::SPITCH + ((4 * k) & (C::SW - 1))) = sbuf[p];
+      // factors, aligned to the receiving cell
+      const v4i_t w0 = sbuf[p][0], w1 = sbuf[p][1];
+      const uint64_t pw = (uint32_t)w0.x | ((uint64_t)(uint32_t)w0.y << 32);
+      const uint64_t pn_own = (uint32_t)w0.z | ((uint64_t)(uint32_t)w0.w << 32);
+      const uint64_t pnw_own = (uint32_t)w1.x | ((uint64_t)(uint32_t)w1.y << 32);
+      const uint64_t pn = shl1z_u32((uint32_t)pn_own) | ((uint64_t)shl1z_u32((uint32_t)(pn_own >> 32)) << 32);
+      const uint64_t pnw = shl1z_u32((uint32_t)pnw_own) | ((uint64_t)shl1z_u32((uint32_t)(pnw_own >> 32)) << 32);
+      const uint64_t fw = (pw >> 1) | (carry_w << 63);       // W selected at slot s+1, own row
+      const uint64_t fn = (pn >> 1) | (carry_n << 63);       // N selected at slot s+1, row r+1
+      const uint64_t fnw = (pnw >> 2) | (carry_nw << 62);    // NW selected at slot s+2, row r+1
+      carry_w = pw & 1u;
+      carry_n = pn & 1u;
+      carry_nw = pnw & 3u;
+      uint32_t* frow = F + lane * C::FPITCH + ((kSub * k) & C::MASK);
+#pragma unroll
+      for (int g = 0; g < 16; ++g) {
+        typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+        const v4u f = {spread4(fw, g), spread4(fn, g), spread4(fnw, g), 0u};
+        *reinterpret_cast<v4u*>(frow + 4 * g) = f;
+      }
+      if (lane == 0) {
+        typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+        const v4u r0 = {(uint32_t)pn_own, (uint32_t)(pn_own >> 32), (uint32_t)pnw_own, (uint32_t)(pnw_own >> 32)};
+        *reinterpret_cast<v4u*>(PubR + 4 * (k & (C::NSUB - 1))) = r0;
+      }
       lds_publish(&sh.ctr[0], (uint32_t)(kr + 1));
-      if (kr + PFS < Ks)
-        sbuf[p] = __builtin_nontemporal_load(reinterpret_cast<const v4i_t*>(selp + (int64_t)(k - PFS) * 256));
-      if (has_g && kr + PF < Ks) adj_load_g<T>(gx, rsrc, ldg, k - PF);
+      }
+      {
+        const v4i_t* src = reinterpret_cast<const v4i_t*>(selp + (int64_t)(k - PFS >= 0 ? k - PFS : 0) * 512);
+        sbuf[p][0] = __builtin_nontemporal_load(src);
+        sbuf[p][1] = __builtin_nontemporal_load(src + 1);
+      }
+      adj_load_g<T>(gx, rsrc, ldg, k - PF >= 0 ? k - PF : 0);
     }
   }
 }
 
-// wave 2: values pushed up by the band below (south and south-east of lane 63), G per unit
+// wave 2: inputs from the band below.  For lane 63 (band row 63) at slot s, column c = s-63,
+// the band below routes pn[c] (its row 0 at column c selected N) and pnw[c+1] (its row 0 at
+// column c+1 selected NW).  The poller folds them into lane 63's upstream value in the value
+// ring, in the order of the sum: (gv + pnw[c+1]) + pn[c].  G slots per unit.
 template <typename T, int G>
-__device__ __forceinline__ void adj_poll(T* Bn, T* Bnw, AdjShared& sh, const AdjArgs& a, int band, int Ks,
-                                         uint32_t epoch) {
+__device__ __forceinline__ void adj_poll(T* S, AdjShared& sh, const AdjArgs& a, int band, int Ks, uint32_t epoch) {
   using C = BCfg<T>;
   using E = typename C::E;
   constexpr int W = E::W;
   const int lane = threadIdx.x & 63;
   const int64_t n = opaque(a.n);
   const int S0 = kSub * Ks, Us = S0 / G;
-  const bool bottom = band == a.nb - 1;
+  if (band == a.nb - 1) {  // the bottom band has nothing below it
+    if (lane == 0) lds_signal(&sh.ctr[1], 0x7fffffffu);
+    return;
+  }
   uint64_t waited = 0;
+  T carry_pnw = E::zero();  // pnw of the first column of the unit processed before (higher slots)
   for (int u = 0; u < Us; ++u) {
-    const int64_t need_steps = (int64_t)G * u + G - C::RING;
-    if (need_steps > 0 && !lds_wait_ge(&sh.ctr[2], (uint32_t)need_steps, &sh.abort, a.ctl, waited)) {
+    const int s = S0 - G * (u + 1) + lane;  // slot of lane 63 handled by this lane's column
+    const int64_t c = (int64_t)s - (kBand - 1);
+    T vn = E::zero(), vnw = E::zero();
+    const bool mine = lane < G && c >= 0 && c < n;
+    const uint64_t* src = a.bnd + ((int64_t)band * n + (mine ? c : 0)) * 2 * W;
+    uint32_t w[2 * W];
+    bool ok = !mine;
+    if (mine) {
+      ok = true;
+#pragma unroll
+      for (int k = 0; k < 2 * W; ++k) {
+        const uint64_t x = load_word(src + k);
+        w[k] = (uint32_t)x;
+        ok = ok && (uint32_t)(x >> 32) == epoch;
+      }
+    }
+    if (!__all(ok)) {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      uint32_t polls = 0;
+      bool give_up = false;
+      while (!__all(ok)) {
+        __builtin_amdgcn_s_sleep(1);
+        if (!ok) {
+          ok = true;
+#pragma unroll
+          for (int k = 0; k < 2 * W; ++k) {
+            const uint64_t x = load_word(src + k);
+            w[k] = (uint32_t)x;
+            ok = ok && (uint32_t)(x >> 32) == epoch;
+          }
+        }
+        if ((++polls & 63u) == 0u) {
+          if (lds_load(&sh.abort) != 0u || global_aborted(a.ctl)) { give_up = true; break; }
+          if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) { raise_timeout(a.ctl); give_up = true; break; }
+        }
+      }
+      waited += __builtin_amdgcn_s_memrealtime() - t0;
+      if (give_up) {
+        sh.abort = 1u;
+        return;
+      }
+    }
+    if (mine) {
+      vn = E::from_words(w);
+      vnw = E::from_words(w + W);
+    }
+    // pnw of column c+1: the next lane's, or for the unit's last lane the carried value
+    T nw_next = shl1z(vnw);
+    if (lane == G - 1) nw_next = carry_pnw;
+    carry_pnw = lane_value(vnw, 0);
+    // the value ring must hold this sub-chunk's upstream values
+    const uint32_t need_l = (uint32_t)((G * u) / kSub + 1);
+    if (!lds_wait_ge(&sh.ctr[0], need_l, &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return;
     }
-    // ring index = slot of lane 63 = column + 63
-    const int idx = S0 - G * (u + 1) + lane;
-    const int64_t c = (int64_t)idx - (kBand - 1);
-    T vn = E::zero(), vnw = E::zero();
-    const bool mine = !bottom && lane < G && c >= 0 && c < n;
-    if (!bottom) {
-      const uint64_t* src = a.bnd + ((int64_t)band * n + (mine ? c : 0)) * 2 * W;
-      uint32_t w[2 * W];
-      bool ok = !mine;
-      if (mine) {
-        ok = true;
-#pragma unroll
-        for (int k = 0; k < 2 * W; ++k) {
-          const uint64_t x = load_word(src + k);
-          w[k] = (uint32_t)x;
-          ok = ok && (uint32_t)(x >> 32) == epoch;
-        }
-      }
-      if (!__all(ok)) {
-        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-        uint32_t polls = 0;
-        bool give_up = false;
-        while (!__all(ok)) {
-          __builtin_amdgcn_s_sleep(1);
-          if (!ok) {
-            ok = true;
-#pragma unroll
-            for (int k = 0; k < 2 * W; ++k) {
-              const uint64_t x = load_word(src + k);
-              w[k] = (uint32_t)x;
-              ok = ok && (uint32_t)(x >> 32) == epoch;
-            }
-          }
-          if ((++polls & 63u) == 0u) {
-            if (lds_load(&sh.abort) != 0u || global_aborted(a.ctl)) { give_up = true; break; }
-            if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) { raise_timeout(a.ctl); give_up = true; break; }
-          }
-        }
-        waited += __builtin_amdgcn_s_memrealtime() - t0;
-        if (give_up) {
-          sh.abort = 1u;
-          return;
-        }
-      }
-      if (mine) {
-        vn = E::from_words(w);
-        vnw = E::from_words(w + W);
-      }
-    }
-    if (lane < G) {
-      Bn[idx & C::MASK] = vn;
-      Bnw[idx & C::MASK] = vnw;
+    if (mine) {
+      T* cell = S + (kBand - 1) * C::PITCH + (s & C::MASK);
+      *cell = E::add(E::add(*cell, nw_next), vn);
     }
     lds_signal(&sh.ctr[1], (uint32_t)(u + 1));
   }
@@ -685,9 +805,10 @@ __device__ __forceinline__ void adj_store(const T* S, AdjShared& sh, const AdjAr
   }
 }
 
-// wave 4: publisher of lane 0's pushes to the band above (north and north-west)
+// wave 4: publisher of row 0's routed values for the band above: at column c (slot c of
+// row 0), A times "selected N" and A times "selected NW".
 template <typename T, int G>
-__device__ __forceinline__ void adj_publish(const T* S, const uint32_t* SelR, AdjShared& sh, const AdjArgs& a,
+__device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, AdjShared& sh, const AdjArgs& a,
                                             int band, int Ks, uint32_t epoch) {
   using C = BCfg<T>;
   using E = typename C::E;
@@ -705,9 +826,10 @@ __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* SelR, Ad
     const int s = S0 - G * (u + 1) + lane;
     if (band > 0 && lane < G && s < n) {
       const T A = S[s & C::MASK];  // row 0
-      const uint32_t code = (SelR[(s >> 4) & (C::SW - 1)] >> (2 * (s & 15))) & 3u;
-      const T pn = code == kSelN ? A : E::zero();
-      const T pnw = code == kSelNW ? A : E::zero();
+      const uint32_t* pr = PubR + 4 * ((s >> 6) & (C::NSUB - 1));
+      const int h = (s >> 5) & 1, bit = s & 31;
+      const T pn = ((pr[h] >> bit) & 1u) ? A : E::zero();
+      const T pnw = ((pr[2 + h] >> bit) & 1u) ? A : E::zero();
       uint64_t* dst = a.bnd + ((int64_t)(band - 1) * n + s) * 2 * W;
 #pragma unroll
       for (int k = 0; k < W; ++k) {
@@ -723,13 +845,10 @@ template <typename T, int G>
 __global__ __launch_bounds__(kThreads, 1) void adj_kernel(AdjArgs a) {
   using C = BCfg<T>;
   __shared__ Vec4<T> S4[kBand * C::PITCH / 4];
-  __shared__ Vec4<T> Bn4[C::RING / 4];
-  __shared__ Vec4<T> Bnw4[C::RING / 4];
-  __shared__ uint32_t SelR[64 * C::SPITCH];
+  __shared__ uint32_t F[kBand * C::FPITCH];
+  __shared__ uint32_t PubR[4 * C::NSUB];
   __shared__ AdjShared sh;
   T* S = reinterpret_cast<T*>(S4);
-  T* Bn = reinterpret_cast<T*>(Bn4);
-  T* Bnw = reinterpret_cast<T*>(Bnw4);
   const int wave = threadIdx.x >> 6;
   Control* ctl = a.ctl;
   const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -743,15 +862,15 @@ __global__ __launch_bounds__(kThreads, 1) void adj_kernel(AdjArgs a) {
     uint64_t* tr = a.trace ? a.trace + (int64_t)band * kTraceWords : nullptr;
     if (tr && threadIdx.x == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
     if (wave == 0)
-      adj_compute<T, G>(S, SelR, Bn, Bnw, sh, ctl, Ks, tr);
+      adj_compute<T, G>(S, F, sh, ctl, Ks, tr);
     else if (wave == 1)
-      adj_loader<T, G>(S, SelR, sh, a, band, Ks);
+      adj_loader<T, G>(S, F, PubR, sh, a, band, Ks);
     else if (wave == 2)
-      adj_poll<T, G>(Bn, Bnw, sh, a, band, Ks, epoch);
+      adj_poll<T, G>(S, sh, a, band, Ks, epoch);
     else if (wave == 3)
       adj_store<T, G>(S, sh, a, band, Ks);
     else
-      adj_publish<T, G>(S, SelR, sh, a, band, Ks, epoch);
+      adj_publish<T, G>(S, PubR, sh, a, band, Ks, epoch);
     if (tr && threadIdx.x == 3 * 64) tr[3] = __builtin_amdgcn_s_memrealtime();
     __syncthreads();
   }

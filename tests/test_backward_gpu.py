@@ -4,7 +4,7 @@ The device recomputes the predecessor selections from C and either the forward t
 the band rows of the checkpoint grid, then runs the reverse sweep.  Bars:
   - float32: bitwise equal to the single-precision oracle's adjoint on the oracle's own
     float32 selection map (the selections match because the forward values match bitwise,
-    and both sides sum the routed terms in the order gD, gscore, NW, W, N);
+    and both sides sum the routed terms in the order gD, gscore, NW, N, W);
   - float64: bitwise equal to the double oracle;
   - the score gradient against central finite differences of the double forward.
 """
