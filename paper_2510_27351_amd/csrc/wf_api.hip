@@ -86,14 +86,17 @@ int words_per_elem(int dtype) { return dtype == WF_F64 ? 2 : 1; }
 namespace {
 
 // Tile width used when the caller has not forced one.
-int choose_tile(int64_t m, int64_t n) {
+// Handoff granularity G.  The forward sweep is fastest with 64 on wide matrices; the
+// reverse sweep, whose compute wave is slower per step, with 32 (measured at 16384 x 16384
+// on MI355X).
+int choose_tile(int64_t m, int64_t n, bool reverse) {
   if (g_tile_override) return g_tile_override;
   if (const char* s = std::getenv("WF_TILE")) {
     int t = std::atoi(s);
     if (t == 16 || t == 32 || t == 64) return t;
   }
   (void)m;
-  return n >= 1024 ? 64 : 32;
+  return n >= 1024 && !reverse ? 64 : 32;
 }
 
 int64_t nbands(int64_t m) { return (m + kBand - 1) / kBand; }
@@ -174,7 +177,7 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
   a.bnd = ws->bnd;
   a.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
   const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
-  const int tile = choose_tile(m, n);
+  const int tile = choose_tile(m, n, false);
   hipError_t e = launch_forward(dtype, tile, a, grid, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
@@ -246,7 +249,7 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   aa.ctl = ws->ctl;
   aa.bnd = ws->bnd;
   aa.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
-  e = launch_adjoint(dtype, choose_tile(m, n), aa, grid, st);
+  e = launch_adjoint(dtype, choose_tile(m, n, true), aa, grid, st);
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
 

@@ -405,7 +405,13 @@ __device__ __forceinline__ void adj_cells4(AdjState<T>& st, const AdjGroup<T>& r
   out.v[0] = adj_cell<T, 0>(st, r);
 }
 
-// Unit u covers slots [S0 - G(u+1), S0 - Gu), groups in descending slot order.
+// Unit u covers slots [S0 - G(u+1), S0 - Gu), groups in descending slot order.  If unit
+// u+1's inputs are already in LDS PD groups before the end (by the counters read at the
+// start of the unit), its first groups are read into 'out' there; otherwise unit u is
+// finished and signalled first and the wave then waits for unit u+1 and reads them.
+// Waiting earlier would hold back the last steps of unit u, and with them row 0's values
+// for the band above, until the band below has delivered unit u+1: one unit of extra lag
+// per band.
 template <typename T, int G>
 __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __restrict__ F, AdjShared& sh,
                                          Control* ctl, int zero, int u, int Us, int S0, AdjState<T>& st,
@@ -416,10 +422,12 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
   const int lane = threadIdx.x & 63;
   const int top = S0 - G * u, next_top = top - G;
   const bool has_next = u + 1 < Us;
+  const uint32_t need_l = (uint32_t)((G * (u + 1)) / kSub + 1), need_b = (uint32_t)(u + 2);
   const uint64_t ready = adj_ready(sh, zero);
   AdjGroup<T> gr[NG + PD];
 #pragma unroll
   for (int p = 0; p < PD; ++p) gr[p] = in.g[p];
+  bool early = false;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (g + PD < NG) {
@@ -427,16 +435,11 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
     } else if (has_next) {
       if (g + PD == NG) {
         __builtin_amdgcn_sched_barrier(0);
-        const uint32_t need_l = (uint32_t)((G * (u + 1)) / kSub + 1), need_b = (uint32_t)(u + 2);
-        if (!__all((uint32_t)ready >= need_l && (uint32_t)(ready >> 32) >= need_b)) {
-          ++stall;
-          if (!lds_wait_ge(&sh.ctr[0], need_l, &sh.abort, ctl, waited) ||
-              !lds_wait_ge(&sh.ctr[1], need_b, &sh.abort, ctl, waited))
-            return false;
-        }
+        early = __all((uint32_t)ready >= need_l && (uint32_t)(ready >> 32) >= need_b);
+        stall += !early;
         __builtin_amdgcn_sched_barrier(0);
       }
-      adj_load_group<T>(S, F, (next_top - 4 * (g + PD - NG + 1)) & C::MASK, lane, out.g[g + PD - NG]);
+      if (early) adj_load_group<T>(S, F, (next_top - 4 * (g + PD - NG + 1)) & C::MASK, lane, out.g[g + PD - NG]);
     }
     __builtin_amdgcn_sched_barrier(0);
     const int b4 = (top - 4 * (g + 1)) & C::MASK;
@@ -446,6 +449,14 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
   }
   lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
   __builtin_amdgcn_sched_barrier(0);
+  if (has_next && !early) {
+    if (!lds_wait_ge(&sh.ctr[0], need_l, &sh.abort, ctl, waited) ||
+        !lds_wait_ge(&sh.ctr[1], need_b, &sh.abort, ctl, waited))
+      return false;
+#pragma unroll
+    for (int p = 0; p < PD; ++p) adj_load_group<T>(S, F, (next_top - 4 * (p + 1)) & C::MASK, lane, out.g[p]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   return true;
 }
 
@@ -663,7 +674,9 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, Ad
 // wave 2: inputs from the band below.  For lane 63 (band row 63) at slot s, column c = s-63,
 // the band below routes pn[c] (its row 0 at column c selected N) and pnw[c+1] (its row 0 at
 // column c+1 selected NW).  The poller folds them into lane 63's upstream value in the value
-// ring, in the order of the sum: (gv + pnw[c+1]) + pn[c].  G slots per unit.
+// ring, in the order of the sum: (gv + pnw[c+1]) + pn[c].  Each pass fetches the words of
+// the 64 slots below the last unit handed over and hands over every complete unit of G
+// slots, so one global round trip advances it by up to 64 slots whatever G is.
 template <typename T, int G>
 __device__ __forceinline__ void adj_poll(T* S, AdjShared& sh, const AdjArgs& a, int band, int Ks, uint32_t epoch) {
   using C = BCfg<T>;
@@ -676,70 +689,105 @@ __device__ __forceinline__ void adj_poll(T* S, AdjShared& sh, const AdjArgs& a, 
     if (lane == 0) lds_signal(&sh.ctr[1], 0x7fffffffu);
     return;
   }
-  uint64_t waited = 0;
-  T carry_pnw = E::zero();  // pnw of the first column of the unit processed before (higher slots)
-  for (int u = 0; u < Us; ++u) {
-    const int s = S0 - G * (u + 1) + lane;  // slot of lane 63 handled by this lane's column
+  uint64_t waited = 0, t0 = 0;
+  uint32_t polls = 0;
+  T carry_pnw = E::zero();  // pnw of the lowest slot handed over so far
+  int u = 0;                // units handed over
+  while (u < Us) {
+    const int s = S0 - G * u - kSub + lane;  // the window: the 64 slots below slot S0 - Gu
     const int64_t c = (int64_t)s - (kBand - 1);
-    T vn = E::zero(), vnw = E::zero();
-    const bool mine = lane < G && c >= 0 && c < n;
-    const uint64_t* src = a.bnd + ((int64_t)band * n + (mine ? c : 0)) * 2 * W;
+    const bool real = c >= 0 && c < n;
+    // Every lane loads on every pass (a lane with no word to read loads spare words of the
+    // control block and ignores them): loads under a lane mask would make each wait drain
+    // all of the wave's loads.  Two polls are in flight: while one pass's words are checked
+    // the next pass's are on their way.
+    const uint64_t* src = real ? a.bnd + ((int64_t)band * n + c) * 2 * W : reinterpret_cast<const uint64_t*>(a.ctl) + 4;
+    uint64_t xa[2 * W], xb[2 * W];
+    auto issue = [&](uint64_t (&x)[2 * W]) {
+#pragma unroll
+      for (int q = 0; q < 2 * W; ++q) x[q] = load_word(src + q);
+    };
+    // units complete in x: the run of ready slots from the top of the window down (slots
+    // outside the matrix count as ready), in whole units
+    auto complete = [&](const uint64_t (&x)[2 * W]) -> int {
+      bool ok = true;
+#pragma unroll
+      for (int q = 0; q < 2 * W; ++q) ok = ok && (uint32_t)(x[q] >> 32) == epoch;
+      ok = ok || !real;
+      const uint64_t okm = __ballot(ok);
+      const int run = ~okm == 0 ? 64 : __builtin_clzll(~okm);
+      const int k = run / G;
+      return k < Us - u ? k : Us - u;
+    };
+    // false when the wait has to give up
+    auto pause = [&]() -> bool {
+      if (polls == 0 && a.trace) t0 = __builtin_amdgcn_s_memrealtime();
+      __builtin_amdgcn_s_sleep(1);
+      if ((++polls & 63u) == 0u) {
+        if (lds_load(&sh.abort) != 0u || global_aborted(a.ctl)) return false;
+        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+        if (polls == 64u) {
+          if (!a.trace) t0 = now;
+        } else if (now - t0 > kSpinTicks) {
+          raise_timeout(a.ctl);
+          return false;
+        }
+      }
+      return true;
+    };
     uint32_t w[2 * W];
-    bool ok = !mine;
-    if (mine) {
-      ok = true;
+    auto take = [&](const uint64_t (&x)[2 * W]) {
 #pragma unroll
-      for (int k = 0; k < 2 * W; ++k) {
-        const uint64_t x = load_word(src + k);
-        w[k] = (uint32_t)x;
-        ok = ok && (uint32_t)(x >> 32) == epoch;
+      for (int q = 0; q < 2 * W; ++q) w[q] = (uint32_t)x[q];
+    };
+    int k;
+    issue(xa);
+    for (;;) {
+      issue(xb);
+      if ((k = complete(xa)) > 0) {
+        take(xa);
+        break;
       }
-    }
-    if (!__all(ok)) {
-      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      uint32_t polls = 0;
-      bool give_up = false;
-      while (!__all(ok)) {
-        __builtin_amdgcn_s_sleep(1);
-        if (!ok) {
-          ok = true;
-#pragma unroll
-          for (int k = 0; k < 2 * W; ++k) {
-            const uint64_t x = load_word(src + k);
-            w[k] = (uint32_t)x;
-            ok = ok && (uint32_t)(x >> 32) == epoch;
-          }
-        }
-        if ((++polls & 63u) == 0u) {
-          if (lds_load(&sh.abort) != 0u || global_aborted(a.ctl)) { give_up = true; break; }
-          if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) { raise_timeout(a.ctl); give_up = true; break; }
-        }
+      if (!pause()) {
+        sh.abort = 1u;
+        return;
       }
-      waited += __builtin_amdgcn_s_memrealtime() - t0;
-      if (give_up) {
+      issue(xa);
+      if ((k = complete(xb)) > 0) {
+        take(xb);
+        break;
+      }
+      if (!pause()) {
         sh.abort = 1u;
         return;
       }
     }
-    if (mine) {
+    if (polls != 0u) {
+      if (a.trace) waited += __builtin_amdgcn_s_memrealtime() - t0;
+      polls = 0;
+    }
+    T vn = E::zero(), vnw = E::zero();
+    if (real) {
       vn = E::from_words(w);
       vnw = E::from_words(w + W);
     }
-    // pnw of column c+1: the next lane's, or for the unit's last lane the carried value
+    const int cols = k * G;
+    // pnw of column c+1: the next lane's, or for the window's top lane the carried value
     T nw_next = shl1z(vnw);
-    if (lane == G - 1) nw_next = carry_pnw;
-    carry_pnw = lane_value(vnw, 0);
-    // the value ring must hold this sub-chunk's upstream values
-    const uint32_t need_l = (uint32_t)((G * u) / kSub + 1);
+    if (lane == kSub - 1) nw_next = carry_pnw;
+    carry_pnw = lane_value(vnw, kSub - cols);
+    // the value ring must hold the upstream values of the units handed over
+    const uint32_t need_l = (uint32_t)((G * (u + k - 1)) / kSub + 1);
     if (!lds_wait_ge(&sh.ctr[0], need_l, &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return;
     }
-    if (mine) {
+    if (real && lane >= kSub - cols) {
       T* cell = S + (kBand - 1) * C::PITCH + (s & C::MASK);
       *cell = E::add(E::add(*cell, nw_next), vn);
     }
-    lds_signal(&sh.ctr[1], (uint32_t)(u + 1));
+    u += k;
+    lds_signal(&sh.ctr[1], (uint32_t)u);
   }
   (void)waited;
 }
@@ -758,7 +806,7 @@ __device__ __forceinline__ void adj_store(const T* S, AdjShared& sh, const AdjAr
   uint64_t waited = 0;
   for (int kr = 0; kr < Ks; ++kr) {
     const int k = Ks - 1 - kr;
-    if (!lds_wait_ge(&sh.ctr[2], (uint32_t)(kSub * (kr + 1)), &sh.abort, a.ctl, waited)) {
+    if (!lds_wait_ge(&sh.ctr[4], (uint32_t)((kSub / G) * (kr + 1)), &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return;
     }
@@ -817,14 +865,20 @@ __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, Ad
   const int64_t n = opaque(a.n);
   const int S0 = kSub * Ks, Us = S0 / G;
   uint64_t waited = 0;
-  for (int u = 0; u < Us; ++u) {
-    if (!lds_wait_ge(&sh.ctr[2], (uint32_t)(G * (u + 1)), &sh.abort, a.ctl, waited)) {
+  for (int u = 0; u < Us;) {
+    uint32_t done;
+    if (!lds_wait_value<true, false>(&sh.ctr[2], (uint32_t)(G * (u + 1)), &sh.abort, a.ctl, waited, done)) {
       sh.abort = 1u;
       return;
     }
-    // lane 0 of the compute wave handled slots [S0 - G(u+1), S0 - Gu) = columns
-    const int s = S0 - G * (u + 1) + lane;
-    if (band > 0 && lane < G && s < n) {
+    // every unit finished by now goes out in this pass, up to 64 slots
+    int k = (int)(done / G) - u;
+    if (k > kSub / G) k = kSub / G;
+    if (k > Us - u) k = Us - u;
+    const int cols = k * G;
+    // lane 0 of the compute wave handled slots [S0 - G(u+k), S0 - Gu) = columns
+    const int s = S0 - G * (u + k) + lane;
+    if (band > 0 && lane < cols && s < n) {
       const T A = S[s & C::MASK];  // row 0
       const uint32_t* pr = PubR + 4 * ((s >> 6) & (C::NSUB - 1));
       const int h = (s >> 5) & 1, bit = s & 31;
@@ -832,18 +886,22 @@ __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, Ad
       const T pnw = ((pr[2 + h] >> bit) & 1u) ? A : E::zero();
       uint64_t* dst = a.bnd + ((int64_t)(band - 1) * n + s) * 2 * W;
 #pragma unroll
-      for (int k = 0; k < W; ++k) {
-        store_word(dst + k, tagged(E::word(pn, k), epoch));
-        store_word(dst + W + k, tagged(E::word(pnw, k), epoch));
+      for (int q = 0; q < W; ++q) {
+        store_word(dst + q, tagged(E::word(pn, q), epoch));
+        store_word(dst + W + q, tagged(E::word(pnw, q), epoch));
       }
     }
-    lds_publish(&sh.ctr[4], (uint32_t)(u + 1));
+    u += k;
+    lds_publish(&sh.ctr[4], (uint32_t)u);
   }
 }
 
-template <typename T, int G>
+// TRACE = false compiles every trace statement out (the production instance); the traced
+// instance is launched only while tracing is enabled.
+template <typename T, int G, bool TRACE>
 __global__ __launch_bounds__(kThreads, 1) void adj_kernel(AdjArgs a) {
   using C = BCfg<T>;
+  if constexpr (!TRACE) a.trace = nullptr;
   __shared__ Vec4<T> S4[kBand * C::PITCH / 4];
   __shared__ uint32_t F[kBand * C::FPITCH];
   __shared__ uint32_t PubR[4 * C::NSUB];
@@ -877,15 +935,20 @@ __global__ __launch_bounds__(kThreads, 1) void adj_kernel(AdjArgs a) {
   finish_launch(ctl, epoch);
 }
 
-template <typename T>
-hipError_t launch_adj_t(int tile, const AdjArgs& a, int grid, hipStream_t s) {
+template <typename T, bool TRACE>
+hipError_t launch_adj_tt(int tile, const AdjArgs& a, int grid, hipStream_t s) {
   switch (tile) {
-    case 16: hipLaunchKernelGGL((adj_kernel<T, 16>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((adj_kernel<T, 32>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 64: hipLaunchKernelGGL((adj_kernel<T, 64>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((adj_kernel<T, 16, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((adj_kernel<T, 32, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((adj_kernel<T, 64, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_t(int tile, const AdjArgs& a, int grid, hipStream_t s) {
+  return a.trace ? launch_adj_tt<T, true>(tile, a, grid, s) : launch_adj_tt<T, false>(tile, a, grid, s);
 }
 
 }  // namespace

@@ -166,16 +166,18 @@ __device__ __forceinline__ void raise_timeout(Control* ctl) {
   __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wave-uniform wait until *p >= need.  Returns false if the launch is being aborted.
-// With check_global = false the wait never touches global memory (a global load would make
-// the wave wait for all of its outstanding loads): the loader uses that form and learns
-// of a global abort through the workgroup's LDS flag, which the other waves raise.
-// 'waited' accumulates the ticks spent spinning (for the optional trace); it is a
-// register-resident reference once inlined.
-template <bool check_global = true>
-__device__ __forceinline__ bool lds_wait_ge(const uint32_t* p, uint32_t need, uint32_t* lds_abort,
-                                            Control* ctl, uint64_t& waited) {
-  if (lds_load(p) >= need) {
+// Wave-uniform wait until *p >= need; 'seen' receives the value that satisfied it.  Returns
+// false if the launch is being aborted.  With check_global = false the wait never touches
+// global memory (a global load would make the wave wait for all of its outstanding loads):
+// the loader uses that form and learns of a global abort through the workgroup's LDS flag,
+// which the other waves raise.  With nap = false the wave re-reads the counter without
+// sleeping in between (for waits on the critical path).  'waited' accumulates the ticks
+// spent spinning (for the optional trace); it is a register-resident reference once inlined.
+template <bool check_global = true, bool nap = true>
+__device__ __forceinline__ bool lds_wait_value(const uint32_t* p, uint32_t need, uint32_t* lds_abort,
+                                               Control* ctl, uint64_t& waited, uint32_t& seen) {
+  seen = lds_load(p);
+  if (seen >= need) {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return true;
   }
@@ -183,8 +185,9 @@ __device__ __forceinline__ bool lds_wait_ge(const uint32_t* p, uint32_t need, ui
   uint32_t polls = 0;
   bool ok = true;
   for (;;) {
-    __builtin_amdgcn_s_sleep(1);
-    if (lds_load(p) >= need) break;
+    if (nap) __builtin_amdgcn_s_sleep(1);
+    seen = lds_load(p);
+    if (seen >= need) break;
     if ((++polls & 255u) == 0u) {
       if (lds_load(lds_abort) != 0u || (check_global && global_aborted(ctl))) {
         ok = false;
@@ -200,6 +203,14 @@ __device__ __forceinline__ bool lds_wait_ge(const uint32_t* p, uint32_t need, ui
   waited += __builtin_amdgcn_s_memrealtime() - t0;
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   return ok;
+}
+
+// Wave-uniform wait until *p >= need.  Returns false if the launch is being aborted.
+template <bool check_global = true>
+__device__ __forceinline__ bool lds_wait_ge(const uint32_t* p, uint32_t need, uint32_t* lds_abort,
+                                            Control* ctl, uint64_t& waited) {
+  uint32_t seen;
+  return lds_wait_value<check_global>(p, need, lds_abort, ctl, waited, seen);
 }
 
 // Counter store for a wave whose earlier LDS writes must be seen first by the readers of

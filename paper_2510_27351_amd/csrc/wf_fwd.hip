@@ -30,12 +30,13 @@
 //                     min3, add), one 16-byte LDS write of D; one broadcast read of the top;
 //   wave 1  loader    64-slot sub-chunks of C: 16R x (16-byte buffer load, 16-byte LDS write)
 //                     per lane, PF sub-chunks in flight in registers;
-//   wave 2  top       polls the band above's tagged boundary words, G columns at a time,
-//                     and fills the top ring;
+//   wave 2  top       polls the band above's tagged boundary words, 64 columns per pass,
+//                     and fills the top ring with every complete unit of G columns;
 //   wave 3  storer    every 64 steps writes the sub-chunk's D back (16-byte LDS read,
 //                     16-byte global store), the checkpoint columns and the score;
-//   wave 4  publisher every G steps publishes the G newly final values of the band's last
-//                     row as tagged words for the band below, and the checkpoint rows.
+//   wave 4  publisher publishes the values of the band's last row that became final since
+//                     its previous pass (whole units of G steps, up to 64 columns) as tagged
+//                     words for the band below, and the checkpoint rows.
 // The publisher has a wave of its own so that nothing delays the handoff, which sits on
 // the critical path of the whole sweep.  G (16/32/64, the "tile width") is the handoff
 // granularity.
@@ -174,25 +175,31 @@ __device__ __forceinline__ void cells4(ComputeState<T, G, R>& st, const GroupReg
   }
 }
 
-// Waits until the C sub-chunk and the top unit that unit u reads are in LDS.
+// Whether the C sub-chunk and the top unit that unit u reads are in LDS, by the counters in
+// 'ready'.
 template <typename T, int G, int R>
-__device__ __forceinline__ bool unit_ready(uint64_t ready, int u, Shared& sh, Control* ctl, uint32_t& stall_c,
-                                           uint32_t& stall_t, uint64_t& waited, bool trace) {
+__device__ __forceinline__ bool unit_in_lds(uint64_t ready, int u) {
   const uint32_t need_c = (uint32_t)((G * u) / kSub + 1);
   const uint32_t need_t = (uint32_t)(u + 1);
-  const bool c_ok = (uint32_t)ready >= need_c, t_ok = (uint32_t)(ready >> 32) >= need_t;
-  if (trace) {
-    stall_c += !c_ok;
-    stall_t += !t_ok;
-  }
-  if (c_ok && t_ok) return true;
+  return (uint32_t)ready >= need_c && (uint32_t)(ready >> 32) >= need_t;
+}
+
+// Waits until the C sub-chunk and the top unit that unit u reads are in LDS.
+template <typename T, int G, int R>
+__device__ __forceinline__ bool unit_wait(int u, Shared& sh, Control* ctl, uint64_t& waited) {
+  const uint32_t need_c = (uint32_t)((G * u) / kSub + 1);
+  const uint32_t need_t = (uint32_t)(u + 1);
   return lds_wait_ge(&sh.ctr[0], need_c, &sh.abort, ctl, waited) &&
          lds_wait_ge(&sh.ctr[1], need_t, &sh.abort, ctl, waited);
 }
 
 // One unit of G steps.  'in' holds the first two groups of unit u (already read); the reads
-// of each later group are issued two groups ahead, and the last two groups issue the reads
-// of unit u+1 into 'out' (after checking that unit u+1 is ready).
+// of each later group are issued two groups ahead.  If unit u+1's inputs are already in LDS
+// two groups before the end (by the counters read at the start of the unit), its first two
+// groups are read into 'out' there; otherwise unit u is finished and signalled first and the
+// wave then waits for unit u+1 and reads them.  Waiting earlier would hold back the last
+// steps of unit u, and with them the band's last row, until the band above has delivered
+// unit u+1: one unit of extra lag per band.
 template <typename T, int G, int R>
 __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restrict__ rowA, const T* __restrict__ rowB,
                                              Shared& sh, Control* ctl,
@@ -210,6 +217,7 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
   GroupRegs<T, G, R> gr[NG + 2];
 #pragma unroll
   for (int p = 0; p < 2; ++p) gr[p] = in.g[p];
+  bool early = false;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (g + 2 < NG) {
@@ -217,10 +225,14 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
     } else if (has_next) {
       if (g + 2 == NG) {
         __builtin_amdgcn_sched_barrier(0);
-        if (!unit_ready<T, G, R>(ready, u + 1, sh, ctl, stall_c, stall_t, waited, trace)) return false;
+        early = __all(unit_in_lds<T, G, R>(ready, u + 1));
+        if (trace && !early) {
+          stall_c += (uint32_t)ready < (uint32_t)((G * (u + 1)) / kSub + 1);
+          stall_t += (uint32_t)(ready >> 32) < (uint32_t)(u + 2);
+        }
         __builtin_amdgcn_sched_barrier(0);
       }
-      load_group<T, G, R>(S, rowA, rowB, next_base + 4 * (g + 2 - NG), lane, out.g[g + 2 - NG]);
+      if (early) load_group<T, G, R>(S, rowA, rowB, next_base + 4 * (g + 2 - NG), lane, out.g[g + 2 - NG]);
     }
     Vec4<T> d[R];
     cells4<T, G, R>(st, gr[g], d);
@@ -229,6 +241,12 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
   }
   lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
   __builtin_amdgcn_sched_barrier(0);
+  if (has_next && !early) {
+    if (!unit_wait<T, G, R>(u + 1, sh, ctl, waited)) return false;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, rowA, rowB, next_base + 4 * p, lane, out.g[p]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   return true;
 }
 
@@ -253,7 +271,7 @@ __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restr
   uint64_t t_first = 0, waited = 0;
   const bool tr = trace != nullptr;
   UnitRegs<T, G, R> P, Q;
-  if (!unit_ready<T, G, R>(load_ready(sh), 0, sh, ctl, stall_c, stall_t, waited, tr)) {
+  if (!unit_in_lds<T, G, R>(load_ready(sh), 0) && !unit_wait<T, G, R>(0, sh, ctl, waited)) {
     sh.abort = 1u;
     return;
   }
@@ -384,7 +402,9 @@ __device__ __forceinline__ void loader_band(T* S, Shared& sh, const FwdArgs& a, 
 }
 
 // ---------------------------------------------------------------------------------------
-// wave 2: top boundary poller, G columns per unit
+// wave 2: top boundary poller.  Each pass fetches the band above's boundary words for the
+// 64 columns from the first unit not yet handed over and hands over every unit of G columns
+// that is complete, so one global round trip advances it by up to 64 columns whatever G is.
 template <typename T, int G, int R>
 __device__ __forceinline__ void top_band(const T* S, T* Tr, Shared& sh, const FwdArgs& a, int band, int Ut,
                                          uint32_t epoch, uint64_t* tr) {
@@ -393,79 +413,115 @@ __device__ __forceinline__ void top_band(const T* S, T* Tr, Shared& sh, const Fw
   constexpr int W = E::W;
   const int lane = threadIdx.x & 63;
   const int64_t n = opaque(a.n);
-  uint64_t waited = 0;
-  // top value of the column before the unit's first: the virtual corner D[-1][-1] = 0 for
+  uint64_t waited = 0, t0 = 0;
+  uint32_t polls = 0;
+  // top value of the column before the pass's first: the virtual corner D[-1][-1] = 0 for
   // the first band, D[row0-1][-1] = +inf for the others
   T last = band == 0 ? E::zero() : E::inf();
-  for (int u = 0; u < Ut; ++u) {
+  int u = 0;  // units handed over
+  while (u < Ut) {
+    const int64_t j0 = (int64_t)G * u;
     // the top ring slot of column j is read at step j and reused RING steps later
-    const int64_t need_steps = (int64_t)G * u + G - C::RING;
+    const int64_t need_steps = j0 + 64 - C::RING;
     if (need_steps > 0 && !lds_wait_ge(&sh.ctr[2], (uint32_t)need_steps, &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return;
     }
-    const int64_t j = (int64_t)G * u + lane;
-    T val = E::inf();
-    if (band > 0) {
-      const bool mine = lane < G && j < n;
-      const uint64_t* src = a.bnd + ((int64_t)(band - 1) * n + (mine ? j : 0)) * W;
+    const int64_t j = j0 + lane;
+    const bool real = j < n;
+    // Every lane loads on every pass (a lane with no word to read loads spare words of the
+    // control block and ignores them): loads under a lane mask would make each wait drain
+    // all of the wave's loads.
+    const bool live = band > 0 && real;
+    const uint64_t* src = live ? a.bnd + ((int64_t)(band - 1) * n + j) * W : reinterpret_cast<const uint64_t*>(a.ctl) + 4;
+    // Two polls in flight: while one pass's words are checked, the next pass's are on their
+    // way, so readiness is seen about half a round trip sooner than with one.
+    uint64_t xa[W], xb[W];
+    auto issue = [&](uint64_t (&x)[W]) {
+#pragma unroll
+      for (int q = 0; q < W; ++q) x[q] = load_word(src + q);
+    };
+    // units complete in x: the leading run of ready columns (columns past the matrix count
+    // as ready), in whole units
+    auto complete = [&](const uint64_t (&x)[W]) -> int {
+      bool ok = true;
+#pragma unroll
+      for (int q = 0; q < W; ++q) ok = ok && (uint32_t)(x[q] >> 32) == epoch;
+      ok = ok || !live;
+      const uint64_t okm = __ballot(ok);
+      const int run = ~okm == 0 ? 64 : __builtin_ctzll(~okm);
+      const int k = run / G;
+      return k < Ut - u ? k : Ut - u;
+    };
+    auto value = [&](const uint64_t (&x)[W]) -> T {
+      if (!live) return E::inf();
       uint32_t w[W];
-      bool ok = !mine;
-      if (mine) {
-        ok = true;
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-          const uint64_t x = load_word(src + k);
-          w[k] = (uint32_t)x;
-          ok = ok && (uint32_t)(x >> 32) == epoch;
+      for (int q = 0; q < W; ++q) w[q] = (uint32_t)x[q];
+      return E::from_words(w);
+    };
+    // false when the wait has to give up
+    auto pause = [&]() -> bool {
+      if (polls == 0 && tr) t0 = __builtin_amdgcn_s_memrealtime();
+      __builtin_amdgcn_s_sleep(1);
+      if ((++polls & 63u) == 0u) {
+        if (lds_load(&sh.abort) != 0u || global_aborted(a.ctl)) return false;
+        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+        if (polls == 64u) {
+          if (!tr) t0 = now;
+        } else if (now - t0 > kSpinTicks) {
+          raise_timeout(a.ctl);
+          return false;
         }
       }
-      if (!__all(ok)) {
-        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-        uint32_t polls = 0;
-        bool give_up = false;
-        while (!__all(ok)) {
-          __builtin_amdgcn_s_sleep(1);
-          if (!ok) {
-            ok = true;
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-              const uint64_t x = load_word(src + k);
-              w[k] = (uint32_t)x;
-              ok = ok && (uint32_t)(x >> 32) == epoch;
-            }
-          }
-          if ((++polls & 63u) == 0u) {
-            if (lds_load(&sh.abort) != 0u || global_aborted(a.ctl)) { give_up = true; break; }
-            if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) { raise_timeout(a.ctl); give_up = true; break; }
-          }
-        }
-        waited += __builtin_amdgcn_s_memrealtime() - t0;
-        if (give_up) {
-          sh.abort = 1u;
-          return;
-        }
+      return true;
+    };
+    T val;
+    int k;
+    issue(xa);
+    for (;;) {
+      issue(xb);
+      if ((k = complete(xa)) > 0) {
+        val = value(xa);
+        break;
       }
-      if (mine) val = E::from_words(w);
+      if (!pause()) {
+        sh.abort = 1u;
+        return;
+      }
+      issue(xa);
+      if ((k = complete(xb)) > 0) {
+        val = value(xb);
+        break;
+      }
+      if (!pause()) {
+        sh.abort = 1u;
+        return;
+      }
     }
+    if (polls != 0u) {
+      if (tr) waited += __builtin_amdgcn_s_memrealtime() - t0;
+      polls = 0;
+    }
+    const int cols = k * G;
     // Row 0's C at these columns (slot = column) must be in LDS before its sums are formed.
-    const uint32_t need_c = (uint32_t)((G * u + G - 1) / kSub + 1);
+    const uint32_t need_c = (uint32_t)((j0 + cols - 1) / kSub + 1);
     if (!lds_wait_ge(&sh.ctr[0], need_c, &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return;
     }
     const T nw = E::shr1(val, last);  // top value one column to the left
-    last = lane_value(val, G - 1);
-    if (lane < G) {
+    last = lane_value(val, cols - 1);
+    if (lane < cols) {
       // TA = C + NW and TB = C + N of row 0, the lane-0 operands of the compute wave
-      const int slot = (G * u + lane) & C::MASK;
+      const int slot = (int)(j & C::MASK);
       const T c0 = S[slot];
-      const bool real = j < n;
       Tr[slot] = real ? E::add(c0, nw) : E::inf();
       Tr[C::RING + slot] = real ? E::add(c0, val) : E::inf();
     }
-    lds_signal(&sh.ctr[1], (uint32_t)(u + 1));
-    if (tr && u == 0 && lane == 0) tr[15] = __builtin_amdgcn_s_memrealtime();
+    u += k;
+    lds_signal(&sh.ctr[1], (uint32_t)u);
+    if (tr && u == k && lane == 0) tr[15] = __builtin_amdgcn_s_memrealtime();
   }
   if (tr && lane == 0) {
     tr[10] = waited;
@@ -546,8 +602,10 @@ __device__ __forceinline__ void store_band(const T* S, Shared& sh, const FwdArgs
                 a.D ? (uint32_t)(((rows - 1) * ldd + n) * (int64_t)sizeof(T)) : 0u);
   uint64_t waited = 0;
   for (int s = 0; s < Ks; ++s) {
-    // sub-chunk s (slots [64s, 64s+64) of every row) is final after step 64s + 63
-    if (!lds_wait_ge(&sh.ctr[2], (uint32_t)(kSub * (s + 1)), &sh.abort, a.ctl, waited)) {
+    // sub-chunk s (slots [64s, 64s+64) of every row) is final after step 64s + 63; its D
+    // goes out after the publisher has issued the boundary words of those steps, which
+    // the band below waits for
+    if (!lds_wait_ge(&sh.ctr[4], (uint32_t)(C::GPS * (s + 1)), &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return;
     }
@@ -588,20 +646,27 @@ __device__ __forceinline__ void publish_band(const T* S, Shared& sh, const FwdAr
   const bool last_band = band == a.nb - 1;
   T* ck_rows = static_cast<T*>(a.ckpt);
   uint64_t waited = 0;
-  for (int u = 0; u < Us; ++u) {
-    if (!lds_wait_ge(&sh.ctr[2], (uint32_t)(G * (u + 1)), &sh.abort, a.ctl, waited)) {
+  for (int u = 0; u < Us;) {
+    uint32_t done;
+    if (!lds_wait_value<true, false>(&sh.ctr[2], (uint32_t)(G * (u + 1)), &sh.abort, a.ctl, waited, done)) {
       sh.abort = 1u;
       return;
     }
-    if (tr && u == 62 / G + 1 && lane == 0) tr[17] = __builtin_amdgcn_s_memrealtime();
-    if (lane < G) {
+    // every unit finished by now goes out in this pass, up to 64 columns
+    int k = (int)(done / G) - u;
+    if (k > kSub / G) k = kSub / G;
+    if (k > Us - u) k = Us - u;
+    const int cols = k * G;
+    const bool mark = tr && u <= 62 / G + 1 && 62 / G + 1 < u + k && lane == 0;
+    if (mark) tr[17] = __builtin_amdgcn_s_memrealtime();
+    if (lane < cols) {
       const int slot = (G * u + lane) & C::MASK;
       // the band's last row, row H-1, finished column Gu + lane - skew(H-1) at this step
       const int64_t j = (int64_t)G * u + lane - C::skew(C::H - 1);
       if (!last_band && j >= 0 && j < n) {
         const T x = S[(C::H - 1) * C::PITCH + slot];
 #pragma unroll
-        for (int k = 0; k < W; ++k) store_word(a.bnd + ((int64_t)band * n + j) * W + k, tagged(E::word(x, k), epoch));
+        for (int q = 0; q < W; ++q) store_word(a.bnd + ((int64_t)band * n + j) * W + q, tagged(E::word(x, q), epoch));
       }
       // checkpoint rows: the last row of every 64-row sub-band except the matrix's last one
       if (ck_rows) {
@@ -614,8 +679,9 @@ __device__ __forceinline__ void publish_band(const T* S, Shared& sh, const FwdAr
         }
       }
     }
-    if (tr && u == 62 / G + 1 && lane == 0) tr[14] = __builtin_amdgcn_s_memrealtime();
-    lds_publish(&sh.ctr[4], (uint32_t)(u + 1));
+    if (mark) tr[14] = __builtin_amdgcn_s_memrealtime();
+    u += k;
+    lds_publish(&sh.ctr[4], (uint32_t)u);
   }
   if (tr && lane == 0) tr[18] = waited;
 }
@@ -647,9 +713,12 @@ __device__ __forceinline__ void run_band(T* S, T* Tr, Shared& sh, const FwdArgs&
   }
 }
 
-template <typename T, int G, int R>
+// TRACE = false compiles every trace statement out (the production instance); the traced
+// instance is launched only while tracing is enabled.
+template <typename T, int G, int R, bool TRACE>
 __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
   using C = FwdCfg<T, G, R>;
+  if constexpr (!TRACE) a.trace = nullptr;
   __shared__ Vec4<T> S4[C::H * C::PITCH / 4];
   __shared__ Vec4<T> Tr4[2 * C::RING / 4];
   __shared__ Shared sh;
@@ -720,15 +789,20 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_batch_kernel(BatchArgs b) {
   finish_launch(ctl, epoch);
 }
 
-template <typename T, int R>
-hipError_t launch_t(int tile, const FwdArgs& a, int grid, hipStream_t s) {
+template <typename T, int R, bool TRACE>
+hipError_t launch_tt(int tile, const FwdArgs& a, int grid, hipStream_t s) {
   switch (tile) {
-    case 16: hipLaunchKernelGGL((fwd_kernel<T, 16, R>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((fwd_kernel<T, 32, R>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 64: hipLaunchKernelGGL((fwd_kernel<T, 64, R>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((fwd_kernel<T, 16, R, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((fwd_kernel<T, 32, R, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((fwd_kernel<T, 64, R, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t launch_t(int tile, const FwdArgs& a, int grid, hipStream_t s) {
+  return a.trace ? launch_tt<T, R, true>(tile, a, grid, s) : launch_tt<T, R, false>(tile, a, grid, s);
 }
 
 template <typename T, int R>
