@@ -405,13 +405,15 @@ __device__ __forceinline__ void adj_cells4(AdjState<T>& st, const AdjGroup<T>& r
   out.v[0] = adj_cell<T, 0>(st, r);
 }
 
-// Unit u covers slots [S0 - G(u+1), S0 - Gu), groups in descending slot order.  If unit
-// u+1's inputs are already in LDS PD groups before the end (by the counters read at the
-// start of the unit), its first groups are read into 'out' there; otherwise unit u is
-// finished and signalled first and the wave then waits for unit u+1 and reads them.
+// Unit u covers slots [S0 - G(u+1), S0 - Gu), groups in descending slot order.  The last
+// PD groups always read unit u+1's first groups into 'out' (so that both paths below leave
+// them in the same registers; conditional reads make the compiler copy every prefetched
+// register at each unit boundary).  If unit u+1's inputs were not yet in LDS PD groups
+// before the end (by the counters read at the start of the unit), unit u is finished and
+// signalled first and the wave then waits for unit u+1 and reads its first groups again.
 // Waiting earlier would hold back the last steps of unit u, and with them row 0's values
 // for the band above, until the band below has delivered unit u+1: one unit of extra lag
-// per band.
+// per band.  After the last unit the reads wrap around the ring and are not used.
 template <typename T, int G>
 __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __restrict__ F, AdjShared& sh,
                                          Control* ctl, int zero, int u, int Us, int S0, AdjState<T>& st,
@@ -427,19 +429,19 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
   AdjGroup<T> gr[NG + PD];
 #pragma unroll
   for (int p = 0; p < PD; ++p) gr[p] = in.g[p];
-  bool early = false;
+  bool early = true;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (g + PD < NG) {
       adj_load_group<T>(S, F, (top - 4 * (g + PD + 1)) & C::MASK, lane, gr[g + PD]);
-    } else if (has_next) {
+    } else {
       if (g + PD == NG) {
         __builtin_amdgcn_sched_barrier(0);
-        early = __all((uint32_t)ready >= need_l && (uint32_t)(ready >> 32) >= need_b);
+        early = !has_next || __all((uint32_t)ready >= need_l && (uint32_t)(ready >> 32) >= need_b);
         stall += !early;
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (early) adj_load_group<T>(S, F, (next_top - 4 * (g + PD - NG + 1)) & C::MASK, lane, out.g[g + PD - NG]);
+      adj_load_group<T>(S, F, (next_top - 4 * (g + PD - NG + 1)) & C::MASK, lane, out.g[g + PD - NG]);
     }
     __builtin_amdgcn_sched_barrier(0);
     const int b4 = (top - 4 * (g + 1)) & C::MASK;
@@ -449,12 +451,15 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
   }
   lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
   __builtin_amdgcn_sched_barrier(0);
-  if (has_next && !early) {
+  if (!early) {
     if (!lds_wait_ge(&sh.ctr[0], need_l, &sh.abort, ctl, waited) ||
         !lds_wait_ge(&sh.ctr[1], need_b, &sh.abort, ctl, waited))
       return false;
+    // The slot is hidden from the optimiser: through the restrict pointers it would take
+    // these reads for repeats of the early ones above and drop them.
+    const int nt = opaque(next_top);
 #pragma unroll
-    for (int p = 0; p < PD; ++p) adj_load_group<T>(S, F, (next_top - 4 * (p + 1)) & C::MASK, lane, out.g[p]);
+    for (int p = 0; p < PD; ++p) adj_load_group<T>(S, F, (nt - 4 * (p + 1)) & C::MASK, lane, out.g[p]);
     __builtin_amdgcn_sched_barrier(0);
   }
   return true;

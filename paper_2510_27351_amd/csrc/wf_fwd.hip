@@ -194,12 +194,15 @@ __device__ __forceinline__ bool unit_wait(int u, Shared& sh, Control* ctl, uint6
 }
 
 // One unit of G steps.  'in' holds the first two groups of unit u (already read); the reads
-// of each later group are issued two groups ahead.  If unit u+1's inputs are already in LDS
-// two groups before the end (by the counters read at the start of the unit), its first two
-// groups are read into 'out' there; otherwise unit u is finished and signalled first and the
-// wave then waits for unit u+1 and reads them.  Waiting earlier would hold back the last
-// steps of unit u, and with them the band's last row, until the band above has delivered
-// unit u+1: one unit of extra lag per band.
+// of each later group are issued two groups ahead, and the last two groups issue the reads
+// of unit u+1's first two groups into 'out' -- always, so that both paths below leave them
+// in the same registers (conditional reads make the compiler copy every prefetched register
+// at each unit boundary).  If unit u+1's inputs were not yet in LDS two groups before the
+// end (by the counters read at the start of the unit), unit u is finished and signalled
+// first and the wave then waits for unit u+1 and reads its first groups again.  Waiting
+// earlier would hold back the last steps of unit u, and with them the band's last row,
+// until the band above has delivered unit u+1: one unit of extra lag per band.  After the
+// last unit the reads wrap around the ring and are not used.
 template <typename T, int G, int R>
 __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restrict__ rowA, const T* __restrict__ rowB,
                                              Shared& sh, Control* ctl,
@@ -217,23 +220,26 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
   GroupRegs<T, G, R> gr[NG + 2];
 #pragma unroll
   for (int p = 0; p < 2; ++p) gr[p] = in.g[p];
-  bool early = false;
+  bool early = true;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (g + 2 < NG) {
       load_group<T, G, R>(S, rowA, rowB, base + 4 * (g + 2), lane, gr[g + 2]);
-    } else if (has_next) {
+    } else {
       if (g + 2 == NG) {
         __builtin_amdgcn_sched_barrier(0);
-        early = __all(unit_in_lds<T, G, R>(ready, u + 1));
+        early = !has_next || __all(unit_in_lds<T, G, R>(ready, u + 1));
         if (trace && !early) {
           stall_c += (uint32_t)ready < (uint32_t)((G * (u + 1)) / kSub + 1);
           stall_t += (uint32_t)(ready >> 32) < (uint32_t)(u + 2);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (early) load_group<T, G, R>(S, rowA, rowB, next_base + 4 * (g + 2 - NG), lane, out.g[g + 2 - NG]);
+      load_group<T, G, R>(S, rowA, rowB, next_base + 4 * (g + 2 - NG), lane, out.g[g + 2 - NG]);
     }
+    // keeps every group's reads two groups ahead of their use (left alone, the scheduler
+    // gathers the reads of several groups into one burst just before the first of them)
+    __builtin_amdgcn_sched_barrier(0);
     Vec4<T> d[R];
     cells4<T, G, R>(st, gr[g], d);
 #pragma unroll
@@ -241,10 +247,13 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
   }
   lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
   __builtin_amdgcn_sched_barrier(0);
-  if (has_next && !early) {
+  if (!early) {
     if (!unit_wait<T, G, R>(u + 1, sh, ctl, waited)) return false;
+    // The slot is hidden from the optimiser: through the restrict pointers it would take
+    // these reads for repeats of the early ones above and drop them.
+    const int nb = opaque(next_base);
 #pragma unroll
-    for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, rowA, rowB, next_base + 4 * p, lane, out.g[p]);
+    for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, rowA, rowB, nb + 4 * p, lane, out.g[p]);
     __builtin_amdgcn_sched_barrier(0);
   }
   return true;
