@@ -87,6 +87,19 @@ struct alignas(8) SelShared {
   uint32_t abort;
 };
 
+// min of two values without the quieting of signalling NaNs that fminf implies for operands
+// the compiler cannot prove canonical (here the DPP-shifted ones): inputs hold no NaN.
+__device__ __forceinline__ float sel_min(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double sel_min(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 template <typename T>
 __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __restrict__ Tr, SelShared& sh,
                                             const SelArgs& a, int band, int Ks) {
@@ -109,8 +122,9 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
     uint32_t pl[3][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      // planes, first step in the most significant bit
-      uint32_t pw = 0, pn = 0, pnw = 0;
+      // per step two bits, first step in the most significant bit: W strictly smaller
+      // than both others, N strictly smaller than NW
+      uint32_t pw = 0, pn = 0;
 #pragma unroll
       for (int g = 0; g < 8; ++g) {
         const int off = base + 32 * h + 4 * g;
@@ -119,19 +133,18 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const T N = E::shr1(X, tv.v[q]);
-          // predecessor: NW unless N is strictly smaller; W if strictly smaller than both
-          const bool n_lt = N < NW;
-          const bool w_lt = X < E::min2(NW, N);
-          pw = (pw << 1) | (uint32_t)w_lt;
-          pn = (pn << 1) | (uint32_t)(n_lt && !w_lt);
-          pnw = (pnw << 1) | (uint32_t)(!n_lt && !w_lt);
-          X = E::add(cv.v[q], E::min3(NW, N, X));
+          const T m = sel_min(NW, N);
+          pn = pn + pn + (uint32_t)(N < NW);
+          pw = pw + pw + (uint32_t)(X < m);
+          X = E::add(cv.v[q], sel_min(m, X));
           NW = N;
         }
       }
       pw = __builtin_bitreverse32(pw);
       pn = __builtin_bitreverse32(pn);
-      pnw = __builtin_bitreverse32(pnw);
+      // predecessor: NW unless N is strictly smaller; W if strictly smaller than both
+      uint32_t pnw = ~pn & ~pw;
+      pn &= ~pw;
       // clear the bits of cells outside the matrix (and of cell (0,0), which selects nothing)
       const int t0 = kSub * k + 32 * h;
       if (!(rows == kBand && t0 >= kBand - 1 && (int64_t)t0 + 32 <= n)) {
