@@ -502,21 +502,17 @@ __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* _
     }
   }
   if (trace) t_first = __builtin_amdgcn_s_memrealtime();
-  AdjUnitRegs<T, G> P, Q;
+  AdjUnitRegs<T, G> P;
 #pragma unroll
   for (int p = 0; p < PD; ++p) adj_load_group<T>(S, F, (S0 - 4 * (p + 1)) & C::MASK, lane, P.g[p]);
-  // Units in pairs, so the next unit's prefetched registers alternate between P and Q.
-  int u = 0;
-  for (; u + 1 < Us; u += 2) {
-    if (!adj_unit<T, G>(S, F, sh, ctl, zero, u, Us, S0, st, P, Q, stall, waited) ||
-        !adj_unit<T, G>(S, F, sh, ctl, zero, u + 1, Us, S0, st, Q, P, stall, waited)) {
+  // One unit per iteration: a unit reads its first groups from P and leaves the next
+  // unit's there (they are dead by the time those reads are issued, so both use the same
+  // registers and nothing is copied at the back edge).
+  for (int u = 0; u < Us; ++u) {
+    if (!adj_unit<T, G>(S, F, sh, ctl, zero, u, Us, S0, st, P, P, stall, waited)) {
       sh.abort = 1u;
       return;
     }
-  }
-  if (u < Us && !adj_unit<T, G>(S, F, sh, ctl, zero, u, Us, S0, st, P, Q, stall, waited)) {
-    sh.abort = 1u;
-    return;
   }
   if (trace && lane == 0) {
     trace[1] = t_first;

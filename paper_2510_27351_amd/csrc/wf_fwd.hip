@@ -279,7 +279,7 @@ __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restr
   uint32_t stall_c = 0, stall_t = 0;
   uint64_t t_first = 0, waited = 0;
   const bool tr = trace != nullptr;
-  UnitRegs<T, G, R> P, Q;
+  UnitRegs<T, G, R> P;
   if (!unit_in_lds<T, G, R>(load_ready(sh), 0) && !unit_wait<T, G, R>(0, sh, ctl, waited)) {
     sh.abort = 1u;
     return;
@@ -287,20 +287,15 @@ __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restr
   if (tr) t_first = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
   for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, rowA, rowB, 4 * p, lane, P.g[p]);
-  // Units in pairs, so the next unit's prefetched registers alternate between P and Q
-  // without copies.
-  int u = 0;
-  for (; u + 1 < Us; u += 2) {
-    if (!compute_unit<T, G, R>(S, rowA, rowB, sh, ctl, u, Us, st, P, Q, stall_c, stall_t, waited, tr) ||
-        !compute_unit<T, G, R>(S, rowA, rowB, sh, ctl, u + 1, Us, st, Q, P, stall_c, stall_t, waited, tr)) {
+  // One unit per iteration: a unit reads its first groups from P and leaves the next
+  // unit's there (they are dead by the time those reads are issued, so both use the same
+  // registers and nothing is copied at the back edge).
+  for (int u = 0; u < Us; ++u) {
+    if (!compute_unit<T, G, R>(S, rowA, rowB, sh, ctl, u, Us, st, P, P, stall_c, stall_t, waited, tr)) {
       sh.abort = 1u;
       return;
     }
-    if (tr && u == 62 / G) trace[16] = __builtin_amdgcn_s_memrealtime();
-  }
-  if (u < Us && !compute_unit<T, G, R>(S, rowA, rowB, sh, ctl, u, Us, st, P, Q, stall_c, stall_t, waited, tr)) {
-    sh.abort = 1u;
-    return;
+    if (tr && u == 62 / G + 1) trace[16] = __builtin_amdgcn_s_memrealtime();
   }
   if (tr && lane == 0) {
     trace[1] = t_first;
