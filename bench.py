@@ -1,17 +1,19 @@
 """Benchmark of the wavefront sweep on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384] [--no-cpu] [--calib-copy]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384] [--no-cpu] [--no-batch]
+                    [--calib-copy]
 
 Workload: one 16384 x 16384 float32 instance, values normal(0,1) clipped to [-4, 4]
 (seed 2), resident in HBM before timing.  A step is the whole differentiable sweep:
   1. wf_forward: the table D, the score and the checkpoint grid (band rows every 64 rows,
      block columns every K = 64 columns), one persistent kernel;
-  2. wf_backward from that checkpoint grid with g_score = 1 (the score's gradient): the
-     selection recompute kernel and the reverse adjoint kernel.
-Prints ONE JSON line: cells/s of the step (value), per-sweep cells/s and effective HBM
-rates (3 m n sizeof(elem) per sweep, 6 m n sizeof(elem) per step), the roofline entry of
-the forward kernel measured with HIP events on its launch stream, and the CPU oracle timed
-on a bounded sample on this host.
+  2. wf_select: the predecessor selections recomputed from C and the checkpoint grid;
+  3. wf_reverse: the reverse sweep with g_score = 1 (the score's gradient).
+(2 and 3 together are wf_backward.)  Prints ONE JSON line: cells/s of the step (value),
+per-sweep cells/s and effective HBM rates (3 m n sizeof(elem) per sweep), per-kernel
+algorithmic HBM rates measured with HIP events on the launch stream, the roofline entry of
+the kernel that takes the longest, and the CPU oracle timed on a bounded sample on this
+host.
 """
 from __future__ import annotations
 
@@ -28,8 +30,13 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0  # MI355X published HBM3E bandwidth
 CKPT_K = 64
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel_f32_16384_traffic.txt")
-FWD_SOURCES = ["wf_fwd.hip", "wf_common.h", "wf_internal.h"]
+PROFILES = os.path.join(ROOT, "profiles")
+# kernel -> (summary file of its measured HBM traffic, sources its code comes from)
+KERNELS = {
+    "fwd_kernel": ("fwd_kernel_f32_16384_traffic.txt", ["wf_fwd.hip", "wf_common.h", "wf_internal.h"]),
+    "sel_kernel": ("sel_kernel_f32_16384_traffic.txt", ["wf_bwd.hip", "wf_common.h", "wf_internal.h"]),
+    "adj_kernel": ("adj_kernel_f32_16384_traffic.txt", ["wf_bwd.hip", "wf_common.h", "wf_internal.h"]),
+}
 
 
 def parse():
@@ -45,24 +52,25 @@ def parse():
     return p.parse_args()
 
 
-def fwd_source_hash() -> str:
+def source_hash(files) -> str:
     h = hashlib.sha256()
-    for f in FWD_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2510_27351_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per forward launch from the committed counter summary, or None when the
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of 'kernel' from the committed counter summary, or None when the
     summary is missing or was taken on other kernel sources."""
+    fname, files = KERNELS[kernel]
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(os.path.join(PROFILES, fname)).read()
     except OSError:
         return None
     src = re.search(r"^source_hash:\s*(\S+)", text, re.M)
     val = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
-    if not src or not val or src.group(1) != fwd_source_hash():
+    if not src or not val or src.group(1) != source_hash(files):
         return None
     return float(val.group(1))
 
@@ -158,9 +166,11 @@ def main():
         wf._lib.check(lib.wf_forward(code, m, n, C.data_ptr(), n, D.data_ptr(), n, wf_score.data_ptr(),
                                      ckpt.data_ptr(), CKPT_K, sp), "wf_forward")
 
-    def bwd():
-        wf._lib.check(lib.wf_backward(code, m, n, C.data_ptr(), n, ckpt.data_ptr(), CKPT_K, None, n,
-                                      one.data_ptr(), None, n, gC.data_ptr(), n, sp), "wf_backward")
+    def select():
+        wf._lib.check(lib.wf_select(code, m, n, C.data_ptr(), n, ckpt.data_ptr(), CKPT_K, None, n, sp), "wf_select")
+
+    def reverse():
+        wf._lib.check(lib.wf_reverse(code, m, n, one.data_ptr(), None, n, gC.data_ptr(), n, sp), "wf_reverse")
 
     wf_score = torch.empty((), dtype=C.dtype, device=dev)
     if args.calib_copy:
@@ -168,11 +178,12 @@ def main():
         torch.cuda.synchronize()
     for _ in range(args.warmup):
         fwd()
-        bwd()
+        select()
+        reverse()
     wf.last_async_error()
     torch.cuda.synchronize()
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -181,23 +192,37 @@ def main():
         ev[k][0].record(stream)
         fwd()
         ev[k][1].record(stream)
-        bwd()
+        select()
         ev[k][2].record(stream)
+        reverse()
+        ev[k][3].record(stream)
     t_end.record(stream)
     torch.cuda.synchronize()
     wf.last_async_error()
     total_ms = t_start.elapsed_time(t_end)
-    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
-    bwd_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    seg = [sum(e[i].elapsed_time(e[i + 1]) for e in ev) / K for i in range(3)]
+    fwd_ms, sel_ms, rev_ms = seg
+    bwd_ms = sel_ms + rev_ms
     ms = total_ms / K
     cells = m * n
     es = C.element_size()
     ck_bytes = ckpt.numel() * es
-    # algorithmic bytes per launch of the forward kernel: read C, write D and the grid
-    fwd_alg = 2 * cells * es + ck_bytes
-    achieved = fwd_alg / (fwd_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    nb = (m + 63) // 64
+    Ks = (n + 63 + 63) // 64
+    plane_bytes = nb * Ks * 64 * 32  # selection bit-planes: 32 bytes per band row and 64 slots
+    top_bytes = (nb - 1) * n * es     # band top rows read back from the checkpoint grid
+    # algorithmic HBM bytes per launch: what each kernel must read and write at least
+    kern = {
+        "fwd_kernel": (fwd_ms, 2 * cells * es + ck_bytes, "read C, write D and the checkpoint grid"),
+        "sel_kernel": (sel_ms, cells * es + top_bytes + plane_bytes,
+                       "read C and the band top rows, write the selection bit-planes"),
+        "adj_kernel": (rev_ms, plane_bytes + cells * es, "read the selection bit-planes, write g_C (g_D absent)"),
+    }
     eff = lambda nbytes, t_ms: nbytes / (t_ms * 1e-3) / 1e9  # noqa: E731
+    kernels = {k: {"ms": t, "bytes_per_launch": b, "achieved_GBps": eff(b, t),
+                   "frac": eff(b, t) / PEAK_HBM_GBPS, "bytes": what}
+               for k, (t, b, what) in kern.items()}
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
     out = {
         "metric": "cells/sec and effective HBM GB/s (% peak), fwd and fwd+adjoint, n=16384",
         "value": cells / (ms * 1e-3),
@@ -213,21 +238,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single {m}x{n} float32, normal(0,1) clipped to [-4,4], seed 2; step = "
                                f"forward (table, score, checkpoint grid K={CKPT_K}) + adjoint of the score "
-                               "from the checkpoint grid",
+                               "from the checkpoint grid (selection recompute + reverse sweep)",
                    "m": m, "n": n, "ckpt_k": CKPT_K},
         "fwd": {"ms": fwd_ms, "cells_per_s": cells / (fwd_ms * 1e-3),
                 "effective_GBps": eff(3 * cells * es, fwd_ms),
                 "effective_pct_peak": 100 * eff(3 * cells * es, fwd_ms) / PEAK_HBM_GBPS},
-        "adjoint": {"ms": bwd_ms, "cells_per_s": cells / (bwd_ms * 1e-3),
+        "adjoint": {"ms": bwd_ms, "select_ms": sel_ms, "reverse_ms": rev_ms, "cells_per_s": cells / (bwd_ms * 1e-3),
                     "effective_GBps": eff(3 * cells * es, bwd_ms),
                     "effective_pct_peak": 100 * eff(3 * cells * es, bwd_ms) / PEAK_HBM_GBPS},
         "fwd_adjoint": {"ms": ms, "effective_GBps": eff(6 * cells * es, ms),
                         "effective_pct_peak": 100 * eff(6 * cells * es, ms) / PEAK_HBM_GBPS},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBPS,
-                     "traffic": traffic,
-                     "kernel": "fwd_kernel<float,64,1>", "kernel_ms": fwd_ms,
-                     "bytes_per_launch": fwd_alg},
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "achieved": kernels[dom]["achieved_GBps"], "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": measured_traffic(dom),
+                     "kernel": dom, "kernel_ms": kernels[dom]["ms"],
+                     "bytes_per_launch": kernels[dom]["bytes_per_launch"]},
     }
     if not args.no_batch:
         b = batch_rate(K, args.warmup)

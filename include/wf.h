@@ -104,6 +104,21 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
                 int64_t ldgd, void* g_C, int64_t ldgc, void* stream);
 
 /*
+ * The two halves of wf_backward, for callers that time or schedule them separately
+ * (wf_backward is exactly wf_select followed by wf_reverse on the same stream).
+ * wf_select recomputes the predecessor selections of an m x n forward sweep (arguments as
+ * for wf_backward) into the calling device's workspace; wf_reverse runs the reverse sweep
+ * from them and writes g_C.  wf_reverse returns WF_E_ARG unless the last wf_select enqueued
+ * on this device was for the same dtype, m and n; the workspace holds one set of
+ * selections per device, so select/reverse pairs on different streams of one device must
+ * not interleave.
+ */
+int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt,
+              int32_t ckpt_k, const void* D, int64_t ldd, void* stream);
+int wf_reverse(int dtype, int64_t m, int64_t n, const void* g_score, const void* g_D, int64_t ldgd,
+               void* g_C, int64_t ldgc, void* stream);
+
+/*
  * Ragged batch.  A plan describes a batch of independent instances of different sizes
  * (instance i: m[i] x n[i], row-major with leading dimension n[i], at element offset
  * offsets[i] of one buffer) and owns a device work list of (instance, band) items.

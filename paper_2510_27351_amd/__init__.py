@@ -110,6 +110,39 @@ def backward(C: torch.Tensor, g_score: torch.Tensor | None = None, g_D: torch.Te
     return g_C
 
 
+def select(C: torch.Tensor, ckpt: torch.Tensor | None = None, ckpt_k: int = 0,
+           D: torch.Tensor | None = None) -> None:
+    """First half of backward: recomputes the predecessor selections of C's forward sweep
+    into the device workspace (wf_select); reverse() then consumes them."""
+    _check_matrix(C)
+    m, n = C.shape
+    if (ckpt is None) == (D is None) or (ckpt is not None and ckpt_k < 1):
+        raise ValueError("pass exactly one of ckpt (with ckpt_k) or D")
+    rc = _lib.load().wf_select(_dtype_code(C), m, n, C.data_ptr(), C.stride(0),
+                               (ckpt.data_ptr() or None) if ckpt is not None else None,
+                               ckpt_k if ckpt is not None else 0,
+                               D.data_ptr() if D is not None else None, D.stride(0) if D is not None else n,
+                               _stream(C.device))
+    _lib.check(rc, "wf_select")
+
+
+def reverse(m: int, n: int, dtype: torch.dtype = torch.float32, g_score: torch.Tensor | None = None,
+            g_D: torch.Tensor | None = None, g_C: torch.Tensor | None = None, device=None) -> torch.Tensor:
+    """Second half of backward: the reverse sweep from the selections of the last select()
+    of this shape on the device (wf_reverse); returns g_C."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    if g_score is not None:
+        g_score = g_score.to(device=dev, dtype=dtype).reshape(()).contiguous()
+    if g_C is None:
+        g_C = torch.empty((m, n), dtype=dtype, device=dev)
+    code = {torch.float32: _lib.WF_F32, torch.float64: _lib.WF_F64, torch.int32: _lib.WF_I32}.get(dtype, -1)
+    rc = _lib.load().wf_reverse(code, m, n, g_score.data_ptr() if g_score is not None else None,
+                                g_D.data_ptr() if g_D is not None else None, g_D.stride(0) if g_D is not None else n,
+                                g_C.data_ptr(), g_C.stride(0), _stream(dev))
+    _lib.check(rc, "wf_reverse")
+    return g_C
+
+
 class WfFunction(torch.autograd.Function):
     """Differentiable sweep: (D, score) = sweep(C), gradient by the adjoint sweep.
 

@@ -34,6 +34,10 @@ def load():
     lib.wf_forward.restype = ctypes.c_int
     lib.wf_backward.argtypes = [ctypes.c_int, i64, i64, p, i64, p, i32, p, i64, p, p, i64, p, i64, p]
     lib.wf_backward.restype = ctypes.c_int
+    lib.wf_select.argtypes = [ctypes.c_int, i64, i64, p, i64, p, i32, p, i64, p]
+    lib.wf_select.restype = ctypes.c_int
+    lib.wf_reverse.argtypes = [ctypes.c_int, i64, i64, p, p, i64, p, i64, p]
+    lib.wf_reverse.restype = ctypes.c_int
     pi64 = ctypes.POINTER(i64)
     lib.wf_plan_create.argtypes = [ctypes.POINTER(p), ctypes.c_int, i32, pi64, pi64, pi64, i32, i32, p]
     lib.wf_plan_create.restype = ctypes.c_int

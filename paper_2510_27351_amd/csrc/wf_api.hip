@@ -182,15 +182,13 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
 
-int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt, int32_t ckpt_k,
-                const void* D, int64_t ldd, const void* g_score, const void* g_D, int64_t ldgd, void* g_C,
-                int64_t ldgc, void* stream) {
+int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt, int32_t ckpt_k,
+              const void* D, int64_t ldd, void* stream) {
   if (dtype != WF_F32 && dtype != WF_F64) return dtype == WF_I32 ? WF_E_UNSUPPORTED : WF_E_ARG;
   const int es = elem_size(dtype);
   if (m < 1 || n < 1 || n > (int64_t)1 << 31 || m > (int64_t)1 << 40) return WF_E_ARG;
   if (m > INT64_MAX / n) return WF_E_ARG;
-  if (!C || !g_C || ldc < n || ldgc < n) return WF_E_ARG;
-  if (g_D && ldgd < n) return WF_E_ARG;
+  if (!C || ldc < n) return WF_E_ARG;
   // exactly one source of the band top rows: the checkpoint grid (ckpt_k > 0) or the table
   if (ckpt_k < 0 || ckpt_k > 4096) return WF_E_ARG;
   if (ckpt_k > 0) {
@@ -199,7 +197,7 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   } else {
     if (D == nullptr || ckpt != nullptr || ldd < n) return WF_E_ARG;
   }
-  if (ldc > kMaxLd / es || ldgc > kMaxLd / es || (g_D && ldgd > kMaxLd / es)) return WF_E_UNSUPPORTED;
+  if (ldc > kMaxLd / es) return WF_E_UNSUPPORTED;
   const int64_t nb = nbands(m);
   if (nb > 0x7fffffff) return WF_E_ARG;
   const int64_t Ks = (n + kBand - 1 + 63) / 64;
@@ -232,9 +230,37 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   sa.Q = (int32_t)(4 * Ks);
   sa.sel = ws->sel;
   sa.ctl = ws->ctl;
-  hipError_t e = launch_select(dtype, sa, grid, st);
-  if (e != hipSuccess) return WF_E_DEVICE;
+  if (launch_select(dtype, sa, grid, st) != hipSuccess) return WF_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  ws->sel_dtype = dtype;
+  ws->sel_m = m;
+  ws->sel_n = n;
+  return WF_OK;
+}
 
+int wf_reverse(int dtype, int64_t m, int64_t n, const void* g_score, const void* g_D, int64_t ldgd, void* g_C,
+               int64_t ldgc, void* stream) {
+  if (dtype != WF_F32 && dtype != WF_F64) return dtype == WF_I32 ? WF_E_UNSUPPORTED : WF_E_ARG;
+  const int es = elem_size(dtype);
+  if (m < 1 || n < 1 || n > (int64_t)1 << 31 || m > (int64_t)1 << 40) return WF_E_ARG;
+  if (m > INT64_MAX / n) return WF_E_ARG;
+  if (!g_C || ldgc < n) return WF_E_ARG;
+  if (g_D && ldgd < n) return WF_E_ARG;
+  if (ldgc > kMaxLd / es || (g_D && ldgd > kMaxLd / es)) return WF_E_UNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  DeviceWs* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev >= (int)g_ws.size()) return WF_E_ARG;
+    ws = &g_ws[dev];
+    // the selections in the workspace must be those of this shape and type
+    if (ws->sel_dtype != dtype || ws->sel_m != m || ws->sel_n != n) return WF_E_ARG;
+  }
+  const int64_t nb = nbands(m);
+  const int64_t Ks = (n + kBand - 1 + 63) / 64;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
   AdjArgs aa;
   aa.sel = ws->sel;
   aa.gD = g_D;
@@ -249,8 +275,28 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   aa.ctl = ws->ctl;
   aa.bnd = ws->bnd;
   aa.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
-  e = launch_adjoint(dtype, choose_tile(m, n, true), aa, grid, st);
+  hipError_t e = launch_adjoint(dtype, choose_tile(m, n, true), aa, grid, st);
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
+}
+
+int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt, int32_t ckpt_k,
+                const void* D, int64_t ldd, const void* g_score, const void* g_D, int64_t ldgd, void* g_C,
+                int64_t ldgc, void* stream) {
+  if (dtype != WF_F32 && dtype != WF_F64) return dtype == WF_I32 ? WF_E_UNSUPPORTED : WF_E_ARG;
+  const int es = elem_size(dtype);
+  // the arguments of both halves are checked before either enqueues work
+  if (m < 1 || n < 1 || n > (int64_t)1 << 31 || m > (int64_t)1 << 40) return WF_E_ARG;
+  if (m > INT64_MAX / n) return WF_E_ARG;
+  if (!C || ldc < n || !g_C || ldgc < n) return WF_E_ARG;
+  if (g_D && ldgd < n) return WF_E_ARG;
+  if (ckpt_k < 0 || ckpt_k > 4096) return WF_E_ARG;
+  if (ckpt_k > 0 ? (D != nullptr || (ckpt == nullptr && wf_ckpt_elems(m, n, ckpt_k) > 0))
+                 : (D == nullptr || ckpt != nullptr || ldd < n))
+    return WF_E_ARG;
+  if (ldc > kMaxLd / es || ldgc > kMaxLd / es || (g_D && ldgd > kMaxLd / es)) return WF_E_UNSUPPORTED;
+  int rc = wf_select(dtype, m, n, C, ldc, ckpt, ckpt_k, D, ldd, stream);
+  if (rc != WF_OK) return rc;
+  return wf_reverse(dtype, m, n, g_score, g_D, ldgd, g_C, ldgc, stream);
 }
 
 int wf_trace_enable(int64_t max_bands) {

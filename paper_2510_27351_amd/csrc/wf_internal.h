@@ -135,6 +135,8 @@ struct DeviceWs {
   size_t bnd_words = 0;
   uint32_t* sel = nullptr;    // selection codes of the adjoint
   size_t sel_words = 0;
+  int sel_dtype = -1;         // dtype, m, n of the last selection recompute enqueued
+  int64_t sel_m = 0, sel_n = 0;
   int num_cus = 0;
 };
 // Returns the workspace of device 'dev' with at least 'words' handoff words.

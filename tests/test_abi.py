@@ -98,3 +98,48 @@ def test_backward_rejects_bad_arguments_before_device_work(lib, case):
                          args["D"], args["ldd"], args["g_score"], args["g_D"], args["ldgd"], args["g_C"],
                          args["ldgc"], args["stream"])
     assert rc == args["expect"], case
+
+
+BAD_SELECT = {
+    "bad dtype": dict(dtype=7),
+    "int32 unsupported": dict(dtype=2, expect=_lib.WF_E_UNSUPPORTED),
+    "m = 0": dict(m=0),
+    "n = 0": dict(n=0),
+    "ldc < n": dict(ldc=3),
+    "null C": dict(C=None),
+    "neither D nor ckpt": dict(D=None),
+    "both D and ckpt": dict(ckpt=0x5000, ckpt_k=64),
+    "k too large": dict(D=None, ckpt=0x5000, ckpt_k=5000),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BAD_SELECT))
+def test_select_rejects_bad_arguments_before_device_work(lib, case):
+    args = dict(dtype=0, m=8, n=8, C=0x1000, ldc=8, ckpt=None, ckpt_k=0, D=0x2000, ldd=8, stream=None,
+                expect=_lib.WF_E_ARG)
+    args.update(BAD_SELECT[case])
+    rc = lib.wf_select(args["dtype"], args["m"], args["n"], args["C"], args["ldc"], args["ckpt"], args["ckpt_k"],
+                       args["D"], args["ldd"], args["stream"])
+    assert rc == args["expect"], case
+
+
+BAD_REVERSE = {
+    "bad dtype": dict(dtype=7),
+    "int32 unsupported": dict(dtype=2, expect=_lib.WF_E_UNSUPPORTED),
+    "m = 0": dict(m=0),
+    "n = 0": dict(n=0),
+    "null g_C": dict(g_C=None),
+    "ldgc < n": dict(ldgc=3),
+    "ldgd < n": dict(ldgd=3),
+    "m*n overflow": dict(m=1 << 40, n=1 << 31, ldgd=1 << 31, ldgc=1 << 31),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BAD_REVERSE))
+def test_reverse_rejects_bad_arguments_before_device_work(lib, case):
+    args = dict(dtype=0, m=8, n=8, g_score=0x3000, g_D=0x4000, ldgd=8, g_C=0x6000, ldgc=8, stream=None,
+                expect=_lib.WF_E_ARG)
+    args.update(BAD_REVERSE[case])
+    rc = lib.wf_reverse(args["dtype"], args["m"], args["n"], args["g_score"], args["g_D"], args["ldgd"],
+                        args["g_C"], args["ldgc"], args["stream"])
+    assert rc == args["expect"], case

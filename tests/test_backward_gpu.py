@@ -208,3 +208,31 @@ def test_backward_argument_errors():
         wf.backward(C, D=D, ckpt=ck, ckpt_k=4)
     with pytest.raises(wf.WfError):
         wf.backward(C.to(torch.int32), D=D.to(torch.int32))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_select_then_reverse_equals_backward(dtype):
+    """wf_select followed by wf_reverse is wf_backward, bit for bit (checkpoint path, with g_D)."""
+    m, n, k = 200, 333, 64
+    C = inputs.normal_clipped(m, n, seed=41).to(dtype).to(DEV)
+    gD = inputs.normal_clipped(m, n, seed=42).to(dtype).to(DEV)
+    gs = torch.tensor(0.5, dtype=dtype, device=DEV)
+    _, _, ck = wf.forward(C, table=False, ckpt_k=k)
+    whole = wf.backward(C, g_score=gs, g_D=gD, ckpt=ck, ckpt_k=k)
+    wf.select(C, ckpt=ck, ckpt_k=k)
+    split = wf.reverse(m, n, dtype, g_score=gs, g_D=gD)
+    wf.last_async_error()
+    assert torch.equal(whole, split)
+
+
+def test_reverse_needs_matching_selections():
+    C = inputs.uniform(40, 50, seed=7).to(DEV)
+    D, _, _ = wf.forward(C)
+    wf.select(C, D=D)
+    with pytest.raises(wf.WfError):
+        wf.reverse(40, 51)  # other shape
+    with pytest.raises(wf.WfError):
+        wf.reverse(40, 50, torch.float64)  # other dtype
+    g = wf.reverse(40, 50, g_score=torch.tensor(1.0))
+    wf.last_async_error()
+    assert torch.equal(g, wf.backward(C, g_score=torch.tensor(1.0, device=DEV), D=D))
