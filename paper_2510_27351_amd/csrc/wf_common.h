@@ -46,6 +46,13 @@ struct Elem<float> {
   __device__ static __forceinline__ float min3(float a, float b, float c) {
     return __builtin_fminf(__builtin_fminf(a, b), c);
   }
+  // v_min3 on operands the compiler cannot prove canonical (DPP-shifted ones): fminf would
+  // quieten each with an extra instruction first.  Inputs hold no NaN.
+  __device__ static __forceinline__ float min3v(float a, float b, float c) {
+    float r;
+    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+  }
   __device__ static __forceinline__ float min2(float a, float b) { return __builtin_fminf(a, b); }
   __device__ static __forceinline__ float add(float c, float v) { return c + v; }
   __device__ static __forceinline__ uint32_t word(float x, int) { return __builtin_bit_cast(uint32_t, x); }
@@ -68,6 +75,7 @@ struct Elem<int32_t> {
     return x < c ? x : c;
   }
   __device__ static __forceinline__ int32_t min2(int32_t a, int32_t b) { return a < b ? a : b; }
+  __device__ static __forceinline__ int32_t min3v(int32_t a, int32_t b, int32_t c) { return min3(a, b, c); }
   // Saturating, so that +inf (INT32_MAX) stays +inf on the virtual border; real cells
   // never saturate under the documented bound on |C|.
   __device__ static __forceinline__ int32_t add(int32_t c, int32_t v) { return __builtin_elementwise_add_sat(c, v); }
@@ -97,6 +105,7 @@ struct Elem<double> {
     return __builtin_fmin(__builtin_fmin(a, b), c);
   }
   __device__ static __forceinline__ double min2(double a, double b) { return __builtin_fmin(a, b); }
+  __device__ static __forceinline__ double min3v(double a, double b, double c) { return min3(a, b, c); }
   __device__ static __forceinline__ double add(double c, double v) { return c + v; }
   __device__ static __forceinline__ uint32_t word(double x, int k) {
     uint64_t b = __builtin_bit_cast(uint64_t, x);

@@ -111,17 +111,16 @@ __device__ __forceinline__ uint64_t load_ready(const Shared& sh) {
 template <typename T, int G, int R>
 struct ComputeState {
   T X[R];   // previous value of each sub-band (W of the next cell)
-  T Xp;     // sub-band 0: the value before that (lane r-1's is the NW of the next cell)
-  T NW[R];  // k >= 1: previous N of the sub-band
+  T NW[R];  // previous N of each sub-band (NW of the next cell)
   T Q[R];   // k >= 1: lane 63 of sub-band k-1 two steps back (rotated to lane 0)
 };
 
-// Per 4-step group: C of every sub-band, and for sub-band 0 the two operands that differ in
-// lane 0 (row 0 of the band), where the top ring supplies C + NW and C + N precomputed.
+// Per 4-step group: C of every sub-band, and the top row's values at the group's columns
+// (read by every lane from the same LDS address; lane 0 takes them).
 template <typename T, int G, int R>
 struct GroupRegs {
   Vec4<T> c[R];
-  Vec4<T> ca, cb;
+  Vec4<T> t;
 };
 
 template <typename T, int G, int R>
@@ -130,42 +129,33 @@ struct UnitRegs {
 };
 
 template <typename T, int G, int R>
-__device__ __forceinline__ void load_group(const T* __restrict__ S, const T* __restrict__ rowA,
-                                           const T* __restrict__ rowB, int slot, int lane, GroupRegs<T, G, R>& r) {
+__device__ __forceinline__ void load_group(const T* __restrict__ S, const T* __restrict__ Tr, int slot, int lane,
+                                           GroupRegs<T, G, R>& r) {
   using C = FwdCfg<T, G, R>;
 #pragma unroll
   for (int k = 0; k < R; ++k) r.c[k] = *reinterpret_cast<const Vec4<T>*>(S + (k * kBand + lane) * C::PITCH + slot);
-  r.ca = *reinterpret_cast<const Vec4<T>*>(rowA + slot);
-  r.cb = *reinterpret_cast<const Vec4<T>*>(rowB + slot);
+  r.t = *reinterpret_cast<const Vec4<T>*>(Tr + slot);
 }
 
-// Four steps.  Sub-band 0 uses  X = min(C + NW, C + W, C + N): rounding is monotone, so
-// this equals C + min(NW, N, W) exactly, and the shifted operands enter through DPP adds
-// (lane 0 reads zero and gets C + NW, C + N from the top ring), which leaves two dependent
-// instructions per step on the chain.  Sub-bands k >= 1 take their lane-0 inputs from
-// lane 63 of sub-band k-1 in registers and use the direct form.
+// Four steps, X = C + min(NW, N, W) per cell.  N is lane r-1's previous value moved by a
+// DPP wave_shr:1 whose "old" operand fills lane 0: for sub-band 0 the top row's value, for
+// sub-band k >= 1 lane 63 of sub-band k-1 from two steps back; NW is the previous N.  Per
+// cell one DPP move, one v_min3, one add, all lanes' chains independent within the step.
 template <typename T, int G, int R>
 __device__ __forceinline__ void cells4(ComputeState<T, G, R>& st, const GroupRegs<T, G, R>& r, Vec4<T> (&out)[R]) {
   using E = Elem<T>;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     T N[R], Qn[R];
+    N[0] = E::shr1(st.X[0], r.t.v[q]);  // lane 0 takes the top row
 #pragma unroll
     for (int k = 1; k < R; ++k) {
       N[k] = E::shr1(st.X[k], st.Q[k]);  // lane 0 takes lane 63 of sub-band k-1
       Qn[k] = ror1(st.X[k - 1]);         // ... for the next step
     }
-    {
-      const T a = E::add(r.ca.v[q], E::shr1z(st.Xp));
-      const T w = E::add(r.c[0].v[q], st.X[0]);
-      const T b = E::add(r.cb.v[q], E::shr1z(st.X[0]));
-      st.Xp = st.X[0];
-      st.X[0] = E::min3(a, w, b);
-      out[0].v[q] = st.X[0];
-    }
 #pragma unroll
-    for (int k = 1; k < R; ++k) {
-      const T v = E::min3(st.NW[k], N[k], st.X[k]);
+    for (int k = 0; k < R; ++k) {
+      const T v = E::min3v(st.NW[k], N[k], st.X[k]);
       st.X[k] = E::add(r.c[k].v[q], v);
       st.NW[k] = N[k];
       out[k].v[q] = st.X[k];
@@ -204,8 +194,7 @@ __device__ __forceinline__ bool unit_wait(int u, Shared& sh, Control* ctl, uint6
 // until the band above has delivered unit u+1: one unit of extra lag per band.  After the
 // last unit the reads wrap around the ring and are not used.
 template <typename T, int G, int R>
-__device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restrict__ rowA, const T* __restrict__ rowB,
-                                             Shared& sh, Control* ctl,
+__device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restrict__ Tr, Shared& sh, Control* ctl,
                                              int u, int Us, ComputeState<T, G, R>& st, const UnitRegs<T, G, R>& in,
                                              UnitRegs<T, G, R>& out, uint32_t& stall_c, uint32_t& stall_t,
                                              uint64_t& waited, bool trace) {
@@ -224,7 +213,7 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     if (g + 2 < NG) {
-      load_group<T, G, R>(S, rowA, rowB, base + 4 * (g + 2), lane, gr[g + 2]);
+      load_group<T, G, R>(S, Tr, base + 4 * (g + 2), lane, gr[g + 2]);
     } else {
       if (g + 2 == NG) {
         __builtin_amdgcn_sched_barrier(0);
@@ -235,7 +224,7 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      load_group<T, G, R>(S, rowA, rowB, next_base + 4 * (g + 2 - NG), lane, out.g[g + 2 - NG]);
+      load_group<T, G, R>(S, Tr, next_base + 4 * (g + 2 - NG), lane, out.g[g + 2 - NG]);
     }
     // keeps every group's reads two groups ahead of their use (left alone, the scheduler
     // gathers the reads of several groups into one burst just before the first of them)
@@ -253,7 +242,7 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
     // these reads for repeats of the early ones above and drop them.
     const int nb = opaque(next_base);
 #pragma unroll
-    for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, rowA, rowB, nb + 4 * p, lane, out.g[p]);
+    for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, Tr, nb + 4 * p, lane, out.g[p]);
     __builtin_amdgcn_sched_barrier(0);
   }
   return true;
@@ -261,8 +250,7 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
 
 template <typename T, int G, int R>
 __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restrict__ Tr, Shared& sh, Control* ctl,
-                                             int Us, uint64_t* trace) {
-  using C = FwdCfg<T, G, R>;
+                                             int Us, bool first_band, uint64_t* trace) {
   using E = Elem<T>;
   const int lane = threadIdx.x & 63;
   ComputeState<T, G, R> st;
@@ -272,10 +260,9 @@ __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restr
     st.NW[k] = E::inf();
     st.Q[k] = E::inf();
   }
-  st.Xp = E::inf();
-  // lane 0 reads C + NW and C + N of row 0 from the top ring (TA, TB), the others their C row
-  const T* rowA = lane == 0 ? Tr : S + lane * C::PITCH;
-  const T* rowB = lane == 0 ? Tr + C::RING : S + lane * C::PITCH;
+  // NW of the band's first cell: the virtual corner D[-1][-1] = 0 for the first band,
+  // D[row0-1][-1] = +inf for the others
+  if (first_band && lane == 0) st.NW[0] = E::zero();
   uint32_t stall_c = 0, stall_t = 0;
   uint64_t t_first = 0, waited = 0;
   const bool tr = trace != nullptr;
@@ -286,12 +273,12 @@ __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restr
   }
   if (tr) t_first = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
-  for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, rowA, rowB, 4 * p, lane, P.g[p]);
+  for (int p = 0; p < 2; ++p) load_group<T, G, R>(S, Tr, 4 * p, lane, P.g[p]);
   // One unit per iteration: a unit reads its first groups from P and leaves the next
   // unit's there (they are dead by the time those reads are issued, so both use the same
   // registers and nothing is copied at the back edge).
   for (int u = 0; u < Us; ++u) {
-    if (!compute_unit<T, G, R>(S, rowA, rowB, sh, ctl, u, Us, st, P, P, stall_c, stall_t, waited, tr)) {
+    if (!compute_unit<T, G, R>(S, Tr, sh, ctl, u, Us, st, P, P, stall_c, stall_t, waited, tr)) {
       sh.abort = 1u;
       return;
     }
@@ -419,9 +406,6 @@ __device__ __forceinline__ void top_band(const T* S, T* Tr, Shared& sh, const Fw
   const int64_t n = opaque(a.n);
   uint64_t waited = 0, t0 = 0;
   uint32_t polls = 0;
-  // top value of the column before the pass's first: the virtual corner D[-1][-1] = 0 for
-  // the first band, D[row0-1][-1] = +inf for the others
-  T last = band == 0 ? E::zero() : E::inf();
   int u = 0;  // units handed over
   while (u < Ut) {
     const int64_t j0 = (int64_t)G * u;
@@ -508,21 +492,7 @@ __device__ __forceinline__ void top_band(const T* S, T* Tr, Shared& sh, const Fw
       polls = 0;
     }
     const int cols = k * G;
-    // Row 0's C at these columns (slot = column) must be in LDS before its sums are formed.
-    const uint32_t need_c = (uint32_t)((j0 + cols - 1) / kSub + 1);
-    if (!lds_wait_ge(&sh.ctr[0], need_c, &sh.abort, a.ctl, waited)) {
-      sh.abort = 1u;
-      return;
-    }
-    const T nw = E::shr1(val, last);  // top value one column to the left
-    last = lane_value(val, cols - 1);
-    if (lane < cols) {
-      // TA = C + NW and TB = C + N of row 0, the lane-0 operands of the compute wave
-      const int slot = (int)(j & C::MASK);
-      const T c0 = S[slot];
-      Tr[slot] = real ? E::add(c0, nw) : E::inf();
-      Tr[C::RING + slot] = real ? E::add(c0, val) : E::inf();
-    }
+    if (lane < cols) Tr[(int)(j & C::MASK)] = real ? val : E::inf();
     u += k;
     lds_signal(&sh.ctr[1], (uint32_t)u);
     if (tr && u == k && lane == 0) tr[15] = __builtin_amdgcn_s_memrealtime();
@@ -702,7 +672,7 @@ __device__ __forceinline__ void run_band(T* S, T* Tr, Shared& sh, const FwdArgs&
   const int Us = Ks * C::GPS;                                          // compute / publish units
   const int Ut = (int)((a.n + G - 1) / G);                             // top units holding real columns
   if (wave == 0) {
-    compute_band<T, G, R>(S, Tr, sh, a.ctl, Us, tr);
+    compute_band<T, G, R>(S, Tr, sh, a.ctl, Us, band == 0, tr);
   } else if (wave == 1) {
     loader_band<T, G, R>(S, sh, a, band, Ks, tr);
   } else if (wave == 2) {
@@ -724,7 +694,7 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
   using C = FwdCfg<T, G, R>;
   if constexpr (!TRACE) a.trace = nullptr;
   __shared__ Vec4<T> S4[C::H * C::PITCH / 4];
-  __shared__ Vec4<T> Tr4[2 * C::RING / 4];
+  __shared__ Vec4<T> Tr4[C::RING / 4];
   __shared__ Shared sh;
   T* S = reinterpret_cast<T*>(S4);
   T* Tr = reinterpret_cast<T*>(Tr4);
@@ -759,7 +729,7 @@ template <typename T, int G, int R>
 __global__ __launch_bounds__(kThreads, 1) void fwd_batch_kernel(BatchArgs b) {
   using C = FwdCfg<T, G, R>;
   __shared__ Vec4<T> S4[C::H * C::PITCH / 4];
-  __shared__ Vec4<T> Tr4[2 * C::RING / 4];
+  __shared__ Vec4<T> Tr4[C::RING / 4];
   __shared__ Shared sh;
   T* S = reinterpret_cast<T*>(S4);
   T* Tr = reinterpret_cast<T*>(Tr4);
