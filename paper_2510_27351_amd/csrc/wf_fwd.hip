@@ -539,21 +539,43 @@ __device__ __forceinline__ void store_sub(const T* S, __amdgpu_buffer_rsrc_t drs
     }
     return;
   }
-  // Edge sub-chunk (first, last, or a partial band): element-wise, only inside the matrix.
-  for (int k = 0; k < 16 * R; ++k) {
-    const int i = 4 * k + (lane >> 4);
-    const int64_t c0 = (int64_t)kSub * s + j4 - C::skew(i);
-    if (i >= rows) continue;
-    const Vec4<T> v = *reinterpret_cast<const Vec4<T>*>(S + i * C::PITCH + slot);
-    const int off = (int)(((int64_t)i * ldd + c0) * (int64_t)sizeof(T));
+  // Edge sub-chunk (first, last, or a partial band): the same 16 LDS reads first, then per
+  // vector one 16-byte store if its four cells lie inside the matrix, else a store per cell
+  // that does.
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (c0 + e >= 0 && c0 + e < n) {
+  for (int h = 0; h < R; ++h) {
+    Vec4<T> v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = 64 * h + 4 * k + (lane >> 4);
+      v[k] = *reinterpret_cast<const Vec4<T>*>(S + i * C::PITCH + slot);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = 64 * h + 4 * k + (lane >> 4);
+      const int64_t c0 = (int64_t)kSub * s + j4 - C::skew(i);
+      if (i >= rows) continue;
+      const int off = (int)(((int64_t)i * ldd + c0) * (int64_t)sizeof(T));
+      if (c0 >= 0 && c0 + 4 <= n) {
         if constexpr (sizeof(T) == 4) {
-          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v.v[e]), drs, off + 4 * e, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v[k]), drs, off, 0, 0);
         } else {
-          typedef int v2i __attribute__((ext_vector_type(2)));
-          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v.v[e]), drs, off + 8 * e, 0, 0);
+          struct Hf { v4i lo, hi; };
+          const Hf hh = __builtin_bit_cast(Hf, v[k]);
+          __builtin_amdgcn_raw_buffer_store_b128(hh.lo, drs, off, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(hh.hi, drs, off + 16, 0, 0);
+        }
+        continue;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (c0 + e >= 0 && c0 + e < n) {
+          if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v[k].v[e]), drs, off + 4 * e, 0, 0);
+          } else {
+            typedef int v2i __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v[k].v[e]), drs, off + 8 * e, 0, 0);
+          }
         }
       }
     }
