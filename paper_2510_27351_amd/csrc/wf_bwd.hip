@@ -308,15 +308,17 @@ __global__ __launch_bounds__(128, 1) void sel_kernel(SelArgs a) {
 }
 
 // =======================================================================================
-// 2. Reverse sweep: five waves, one 64-row band per workgroup, bands from the bottom up.
+// 2. Reverse sweep: six waves, one 64-row band per workgroup, bands from the bottom up.
 // =======================================================================================
 struct alignas(8) AdjShared {
-  uint32_t ctr[6];  // 0: sub-chunks loaded (upstream values + factors), 1: units whose lane-63
-                    // inputs from the band below are added in, 2: reverse steps done,
-                    // 3: sub-chunks stored, 4: units published
+  uint32_t ctr[7];  // 0: sub-chunks of upstream values loaded, 1: units whose lane-63 inputs
+                    // from the band below are added in, 2: reverse steps done, 3: sub-chunks
+                    // stored, 4: units published, 5: unused, 6: sub-chunks of factors loaded
   uint32_t item;
   uint32_t abort;
 };
+constexpr int kAdjCounters = 7;
+constexpr int kAdjThreads = 6 * 64;
 
 // Both readiness counters of the compute wave in one 8-byte LDS read.  'zero' is 0, but
 // the compiler cannot tell: the value counts as per-lane data and is compared where it is
@@ -325,6 +327,16 @@ struct alignas(8) AdjShared {
 __device__ __forceinline__ uint64_t adj_ready(const AdjShared& sh, int zero) {
   return __hip_atomic_load(reinterpret_cast<const uint64_t*>(&sh.ctr[0]) + zero, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t adj_ready_f(const AdjShared& sh, int zero) {
+  return __hip_atomic_load(&sh.ctr[6] + zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Whether the compute wave's inputs are in LDS: need_l sub-chunks of values and of factors,
+// need_b units of the band below's inputs (all three counters read before any compare).
+__device__ __forceinline__ bool adj_inputs_ready(const AdjShared& sh, int zero, uint32_t need_l, uint32_t need_b) {
+  const uint64_t r = adj_ready(sh, zero);
+  const uint32_t f = adj_ready_f(sh, zero);
+  return __all((uint32_t)r >= need_l && (uint32_t)(r >> 32) >= need_b && f >= need_l);
 }
 __device__ __forceinline__ int adj_opaque_zero() {
   int z = 0;
@@ -439,6 +451,7 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
   const bool has_next = u + 1 < Us;
   const uint32_t need_l = (uint32_t)((G * (u + 1)) / kSub + 1), need_b = (uint32_t)(u + 2);
   const uint64_t ready = adj_ready(sh, zero);
+  const uint32_t ready_f = adj_ready_f(sh, zero);
   AdjGroup<T> gr[NG + PD];
 #pragma unroll
   for (int p = 0; p < PD; ++p) gr[p] = in.g[p];
@@ -450,7 +463,7 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
     } else {
       if (g + PD == NG) {
         __builtin_amdgcn_sched_barrier(0);
-        early = !has_next || __all((uint32_t)ready >= need_l && (uint32_t)(ready >> 32) >= need_b);
+        early = !has_next || __all((uint32_t)ready >= need_l && (uint32_t)(ready >> 32) >= need_b && ready_f >= need_l);
         stall += !early;
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -465,8 +478,7 @@ __device__ __forceinline__ bool adj_unit(T* __restrict__ S, const uint32_t* __re
   lds_signal(&sh.ctr[2], (uint32_t)(G * (u + 1)));
   __builtin_amdgcn_sched_barrier(0);
   if (!early) {
-    if (!lds_wait_ge(&sh.ctr[0], need_l, &sh.abort, ctl, waited) ||
-        !lds_wait_ge(&sh.ctr[1], need_b, &sh.abort, ctl, waited))
+    if (!lds_wait_until([&] { return adj_inputs_ready(sh, zero, need_l, need_b); }, &sh.abort, ctl, waited))
       return false;
     // The slot is hidden from the optimiser: through the restrict pointers it would take
     // these reads for repeats of the early ones above and drop them.
@@ -492,10 +504,9 @@ __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* _
   uint32_t stall = 0;
   const int zero = adj_opaque_zero();
   {
-    const uint64_t ready = adj_ready(sh, zero);
-    if (!__all((uint32_t)ready >= 1u && (uint32_t)(ready >> 32) >= 1u)) {
+    if (!adj_inputs_ready(sh, zero, 1u, 1u)) {
       ++stall;
-      if (!lds_wait_ge(&sh.ctr[0], 1u, &sh.abort, ctl, waited) || !lds_wait_ge(&sh.ctr[1], 1u, &sh.abort, ctl, waited)) {
+      if (!lds_wait_until([&] { return adj_inputs_ready(sh, zero, 1u, 1u); }, &sh.abort, ctl, waited)) {
         sh.abort = 1u;
         return;
       }
@@ -513,6 +524,8 @@ __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* _
       sh.abort = 1u;
       return;
     }
+    // the first unit whose row 0 the band above's first unit needs is done
+    if (trace && u == (G + kBand - 1) / G) trace[16] = __builtin_amdgcn_s_memrealtime();
   }
   if (trace && lane == 0) {
     trace[1] = t_first;
@@ -522,9 +535,10 @@ __device__ __forceinline__ void adj_compute(T* __restrict__ S, const uint32_t* _
   }
 }
 
-// wave 1: loader, one 64-slot sub-chunk at a time from the top slot down:
+// waves 1 and 5: loaders, one 64-slot sub-chunk at a time from the top slot down.  Wave 1:
 //  - upstream values gD (plus gscore on the last cell; zeros when gD is absent) into the
-//    value ring;
+//    value ring.
+// Wave 5:
 //  - the factor words: for the cell of lane r at slot s, byte 0 of the W word says whether
 //    cell (r, slot s+1) selected W, byte 0 of the N word whether (r+1, s+1) selected N, byte
 //    0 of the NW word whether (r+1, s+2) selected NW -- i.e. whether that successor routes
@@ -568,9 +582,13 @@ __device__ __forceinline__ uint32_t spread4(uint64_t bits, int g) {
   return (nib * 0x00204081u) & 0x01010101u;
 }
 
-template <typename T, int G>
+// Two waves share the loading: PART 0 writes the upstream values (HAS_G: whether gD is
+// given; without it no loads are issued at all) and counts them in ctr[0], PART 1 the factor
+// words and row 0's planes, counted in ctr[6].  One wave doing both falls behind the reverse
+// chain: it spends longer per sub-chunk than the chain takes to consume it.
+template <typename T, int G, bool HAS_G, int PART>
 __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, AdjShared& sh, const AdjArgs& a,
-                                           int band, int Ks) {
+                                           int band, int Ks, uint64_t* tr) {
   using C = BCfg<T>;
   using E = typename C::E;
   constexpr int PF = AdjPF<T>::PF, PFS = AdjPF<T>::PFS;
@@ -579,13 +597,9 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, Ad
   const int64_t ldg = opaque(a.ldgd), n = opaque(a.n), m = opaque(a.m);
   const int64_t row0 = (int64_t)band * kBand;
   const int rows = (int)(m - row0 < kBand ? m - row0 : kBand);
-  // Without gD the buffer covers no bytes: the loads still issue (so that every sub-chunk
-  // has the same loads in flight and the compiler can wait for the oldest only) and return
-  // zeros.
-  const bool has_g = a.gD != nullptr;
   const __amdgpu_buffer_rsrc_t rsrc =
-      make_rsrc(has_g ? static_cast<const T*>(a.gD) + row0 * ldg : a.gC,
-                has_g ? (uint32_t)(((rows - 1) * ldg + n) * (int64_t)sizeof(T)) : 0u);
+      make_rsrc(HAS_G ? static_cast<const T*>(a.gD) + row0 * ldg : a.gC,
+                HAS_G ? (uint32_t)(((rows - 1) * ldg + n) * (int64_t)sizeof(T)) : 0u);
   // gscore lands on cell (m-1, n-1): band row m-1-row0, slot n-1 + that row
   const int64_t last_row = m - 1 - row0;
   const bool has_last = last_row >= 0 && last_row < kBand && a.gscore != nullptr;
@@ -593,27 +607,32 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, Ad
   const int64_t last_slot = n - 1 + last_row;
   const uint32_t* selp = a.sel + sel_index(band, Ks, 0, lane);  // + 512 words per sub-chunk
   uint64_t waited = 0;
-  Vec4<T> gbuf[PF][16];
-  v4i_t sbuf[PFS][2];
+  constexpr bool LOAD_G = PART == 0 && HAS_G;
+  Vec4<T> gbuf[LOAD_G ? PF : 1][16];
+  v4i_t sbuf[PART == 1 ? PFS : 1][2];
   // bits of the slots just above the current sub-chunk (the one processed before it)
   uint64_t carry_w = 0, carry_n = 0, carry_nw = 0;
   // reverse order: the kr-th sub-chunk processed is k = Ks-1-kr
   // Loads are issued unconditionally (indices clamped to sub-chunk 0), PFS / PF sub-chunks
   // ahead, so that the number in flight is the same at every wait.
+  if constexpr (PART == 1) {
 #pragma unroll
-  for (int p = 0; p < PFS; ++p) {
-    const v4i_t* src = reinterpret_cast<const v4i_t*>(selp + (int64_t)(Ks - 1 - p >= 0 ? Ks - 1 - p : 0) * 512);
-    sbuf[p][0] = __builtin_nontemporal_load(src);
-    sbuf[p][1] = __builtin_nontemporal_load(src + 1);
+    for (int p = 0; p < PFS; ++p) {
+      const v4i_t* src = reinterpret_cast<const v4i_t*>(selp + (int64_t)(Ks - 1 - p >= 0 ? Ks - 1 - p : 0) * 512);
+      sbuf[p][0] = __builtin_nontemporal_load(src);
+      sbuf[p][1] = __builtin_nontemporal_load(src + 1);
+    }
   }
+  if constexpr (LOAD_G) {
 #pragma unroll
-  for (int p = 0; p < PF; ++p) adj_load_g<T>(gbuf[p], rsrc, ldg, Ks - 1 - p >= 0 ? Ks - 1 - p : 0);
+    for (int p = 0; p < PF; ++p) adj_load_g<T>(gbuf[p], rsrc, ldg, Ks - 1 - p >= 0 ? Ks - 1 - p : 0);
+  }
   for (int kr0 = 0; kr0 < Ks; kr0 += PFS) {
 #pragma unroll
     for (int p = 0; p < PFS; ++p) {
       const int kr = kr0 + p;
       const int k = Ks - 1 - kr;  // sub-chunk (slots [64k, 64k+64))
-      Vec4<T>(&gx)[16] = gbuf[p % PF];
+      Vec4<T>(&gx)[16] = gbuf[LOAD_G ? p % PF : 0];
       if (kr < Ks) {
       const int older = kr - C::NSUB;
       if (older >= 0 && (!lds_wait_ge<false>(&sh.ctr[3], (uint32_t)(older + 1), &sh.abort, a.ctl, waited) ||
@@ -622,6 +641,7 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, Ad
         sh.abort = 1u;
         return;
       }
+      if constexpr (PART == 0) {
       // upstream values
       const bool interior = rows == kBand && k > 0 && (int64_t)kSub * k + kSub <= n;
 #pragma unroll
@@ -630,7 +650,7 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, Ad
         const int slot = kSub * k + 4 * (lane & 15);
         const int64_t c0 = (int64_t)slot - i;
         Vec4<T> x;
-        if (has_g) {
+        if constexpr (HAS_G) {
           x = gx[v];
           if (!interior) {
 #pragma unroll
@@ -648,8 +668,10 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, Ad
         }
         *reinterpret_cast<Vec4<T>*>(S + i * C::PITCH + (slot & C::MASK)) = x;
       }
+      lds_publish(&sh.ctr[0], (uint32_t)(kr + 1));
+      } else {
       // factors, aligned to the receiving cell
-      const v4i_t w0 = sbuf[p][0], w1 = sbuf[p][1];
+      const v4i_t w0 = sbuf[p % PFS][0], w1 = sbuf[p % PFS][1];
       const uint64_t pw = (uint32_t)w0.x | ((uint64_t)(uint32_t)w0.y << 32);
       const uint64_t pn_own = (uint32_t)w0.z | ((uint64_t)(uint32_t)w0.w << 32);
       const uint64_t pnw_own = (uint32_t)w1.x | ((uint64_t)(uint32_t)w1.y << 32);
@@ -673,15 +695,20 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, Ad
         const v4u r0 = {(uint32_t)pn_own, (uint32_t)(pn_own >> 32), (uint32_t)pnw_own, (uint32_t)(pnw_own >> 32)};
         *reinterpret_cast<v4u*>(PubR + 4 * (k & (C::NSUB - 1))) = r0;
       }
-      lds_publish(&sh.ctr[0], (uint32_t)(kr + 1));
+      lds_publish(&sh.ctr[6], (uint32_t)(kr + 1));
       }
-      {
+      }
+      if constexpr (PART == 1) {
         const v4i_t* src = reinterpret_cast<const v4i_t*>(selp + (int64_t)(k - PFS >= 0 ? k - PFS : 0) * 512);
         sbuf[p][0] = __builtin_nontemporal_load(src);
         sbuf[p][1] = __builtin_nontemporal_load(src + 1);
       }
-      adj_load_g<T>(gx, rsrc, ldg, k - PF >= 0 ? k - PF : 0);
+      if constexpr (LOAD_G) adj_load_g<T>(gx, rsrc, ldg, k - PF >= 0 ? k - PF : 0);
     }
+  }
+  if (PART == 0 && tr && lane == 0) {
+    tr[9] = waited;
+    tr[12] = __builtin_amdgcn_s_memrealtime();
   }
 }
 
@@ -692,7 +719,8 @@ __device__ __forceinline__ void adj_loader(T* S, uint32_t* F, uint32_t* PubR, Ad
 // the 64 slots below the last unit handed over and hands over every complete unit of G
 // slots, so one global round trip advances it by up to 64 slots whatever G is.
 template <typename T, int G>
-__device__ __forceinline__ void adj_poll(T* S, AdjShared& sh, const AdjArgs& a, int band, int Ks, uint32_t epoch) {
+__device__ __forceinline__ void adj_poll(T* S, AdjShared& sh, const AdjArgs& a, int band, int Ks, uint32_t epoch,
+                                         uint64_t* tr) {
   using C = BCfg<T>;
   using E = typename C::E;
   constexpr int W = E::W;
@@ -802,13 +830,14 @@ __device__ __forceinline__ void adj_poll(T* S, AdjShared& sh, const AdjArgs& a, 
     }
     u += k;
     lds_signal(&sh.ctr[1], (uint32_t)u);
+    if (tr && lane == 0 && u == k) tr[15] = __builtin_amdgcn_s_memrealtime();
   }
-  (void)waited;
+  if (tr && lane == 0) tr[10] = waited;
 }
 
 // wave 3: storer of gC (= A), one sub-chunk at a time from the top slot down
 template <typename T, int G>
-__device__ __forceinline__ void adj_store(const T* S, AdjShared& sh, const AdjArgs& a, int band, int Ks) {
+__device__ __forceinline__ void adj_store(const T* S, AdjShared& sh, const AdjArgs& a, int band, int Ks, uint64_t* tr) {
   using C = BCfg<T>;
   typedef int v4i __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
@@ -844,20 +873,36 @@ __device__ __forceinline__ void adj_store(const T* S, AdjShared& sh, const AdjAr
         }
       }
     } else {
+      // edge sub-chunk: the same 16 LDS reads first, then per vector one 16-byte store if its
+      // four cells lie inside the matrix, else a store per cell that does
+      Vec4<T> v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = *reinterpret_cast<const Vec4<T>*>(S + (4 * q + (lane >> 4)) * C::PITCH + slot);
+#pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int i = 4 * q + (lane >> 4);
         if (i >= rows) continue;
         const int64_t c0 = (int64_t)kSub * k + j4 - i;
-        const Vec4<T> v = *reinterpret_cast<const Vec4<T>*>(S + i * C::PITCH + slot);
         const int off = (int)(((int64_t)i * ldo + c0) * (int64_t)sizeof(T));
+        if (c0 >= 0 && c0 + 4 <= n) {
+          if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v[q]), drs, off, 0, 0);
+          } else {
+            struct Hf { v4i lo, hi; };
+            const Hf hh = __builtin_bit_cast(Hf, v[q]);
+            __builtin_amdgcn_raw_buffer_store_b128(hh.lo, drs, off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(hh.hi, drs, off + 16, 0, 0);
+          }
+          continue;
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           if (c0 + e >= 0 && c0 + e < n) {
             if constexpr (sizeof(T) == 4) {
-              __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v.v[e]), drs, off + 4 * e, 0, 0);
+              __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v[q].v[e]), drs, off + 4 * e, 0, 0);
             } else {
               typedef int v2i __attribute__((ext_vector_type(2)));
-              __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v.v[e]), drs, off + 8 * e, 0, 0);
+              __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v[q].v[e]), drs, off + 8 * e, 0, 0);
             }
           }
         }
@@ -865,13 +910,14 @@ __device__ __forceinline__ void adj_store(const T* S, AdjShared& sh, const AdjAr
     }
     lds_publish(&sh.ctr[3], (uint32_t)(kr + 1));
   }
+  if (tr && lane == 0) tr[11] = waited;
 }
 
 // wave 4: publisher of row 0's routed values for the band above: at column c (slot c of
 // row 0), A times "selected N" and A times "selected NW".
 template <typename T, int G>
 __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, AdjShared& sh, const AdjArgs& a,
-                                            int band, int Ks, uint32_t epoch) {
+                                            int band, int Ks, uint32_t epoch, uint64_t* tr) {
   using C = BCfg<T>;
   using E = typename C::E;
   constexpr int W = E::W;
@@ -890,6 +936,8 @@ __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, Ad
     if (k > kSub / G) k = kSub / G;
     if (k > Us - u) k = Us - u;
     const int cols = k * G;
+    const bool mark = tr && lane == 0 && u <= (G + kBand - 1) / G && (G + kBand - 1) / G < u + k;
+    if (mark) tr[17] = __builtin_amdgcn_s_memrealtime();
     // lane 0 of the compute wave handled slots [S0 - G(u+k), S0 - Gu) = columns
     const int s = S0 - G * (u + k) + lane;
     if (band > 0 && lane < cols && s < n) {
@@ -905,15 +953,17 @@ __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, Ad
         store_word(dst + W + q, tagged(E::word(pnw, q), epoch));
       }
     }
+    if (mark) tr[14] = __builtin_amdgcn_s_memrealtime();
     u += k;
     lds_publish(&sh.ctr[4], (uint32_t)u);
   }
+  if (tr && lane == 0) tr[18] = waited;
 }
 
 // TRACE = false compiles every trace statement out (the production instance); the traced
 // instance is launched only while tracing is enabled.
 template <typename T, int G, bool TRACE>
-__global__ __launch_bounds__(kThreads, 1) void adj_kernel(AdjArgs a) {
+__global__ __launch_bounds__(kAdjThreads, 1) void adj_kernel(AdjArgs a) {
   using C = BCfg<T>;
   if constexpr (!TRACE) a.trace = nullptr;
   __shared__ Vec4<T> S4[kBand * C::PITCH / 4];
@@ -927,7 +977,7 @@ __global__ __launch_bounds__(kThreads, 1) void adj_kernel(AdjArgs a) {
   const int Ks = (int)((a.n + kBand - 1 + kSub - 1) / kSub);
   if (threadIdx.x == 0) sh.abort = 0u;
   for (;;) {
-    if (threadIdx.x < 6) sh.ctr[threadIdx.x] = 0u;
+    if (threadIdx.x < kAdjCounters) sh.ctr[threadIdx.x] = 0u;
     claim_next(ctl, &sh.item, &sh.abort);
     if (sh.item >= (uint32_t)a.nb || sh.abort != 0u) break;
     const int band = a.nb - 1 - (int)sh.item;  // bottom band first
@@ -936,13 +986,16 @@ __global__ __launch_bounds__(kThreads, 1) void adj_kernel(AdjArgs a) {
     if (wave == 0)
       adj_compute<T, G>(S, F, sh, ctl, Ks, tr);
     else if (wave == 1)
-      adj_loader<T, G>(S, F, PubR, sh, a, band, Ks);
+      a.gD ? adj_loader<T, G, true, 0>(S, F, PubR, sh, a, band, Ks, tr)
+           : adj_loader<T, G, false, 0>(S, F, PubR, sh, a, band, Ks, tr);
     else if (wave == 2)
-      adj_poll<T, G>(S, sh, a, band, Ks, epoch);
+      adj_poll<T, G>(S, sh, a, band, Ks, epoch, tr);
     else if (wave == 3)
-      adj_store<T, G>(S, sh, a, band, Ks);
+      adj_store<T, G>(S, sh, a, band, Ks, tr);
+    else if (wave == 4)
+      adj_publish<T, G>(S, PubR, sh, a, band, Ks, epoch, tr);
     else
-      adj_publish<T, G>(S, PubR, sh, a, band, Ks, epoch);
+      adj_loader<T, G, false, 1>(S, F, PubR, sh, a, band, Ks, tr);
     if (tr && threadIdx.x == 3 * 64) tr[3] = __builtin_amdgcn_s_memrealtime();
     __syncthreads();
   }
@@ -952,9 +1005,9 @@ __global__ __launch_bounds__(kThreads, 1) void adj_kernel(AdjArgs a) {
 template <typename T, bool TRACE>
 hipError_t launch_adj_tt(int tile, const AdjArgs& a, int grid, hipStream_t s) {
   switch (tile) {
-    case 16: hipLaunchKernelGGL((adj_kernel<T, 16, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((adj_kernel<T, 32, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 64: hipLaunchKernelGGL((adj_kernel<T, 64, TRACE>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((adj_kernel<T, 16, TRACE>), dim3(grid), dim3(kAdjThreads), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((adj_kernel<T, 32, TRACE>), dim3(grid), dim3(kAdjThreads), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((adj_kernel<T, 64, TRACE>), dim3(grid), dim3(kAdjThreads), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

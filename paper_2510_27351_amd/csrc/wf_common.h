@@ -214,6 +214,38 @@ __device__ __forceinline__ bool lds_wait_value(const uint32_t* p, uint32_t need,
   return ok;
 }
 
+// Wave-uniform wait until ready() holds, for a condition on several LDS counters: ready()
+// issues all of its counter reads before it compares, so a satisfied condition costs one LDS
+// round trip rather than one per counter.  No sleep between polls (for the critical path);
+// otherwise bounded like lds_wait_value.
+template <typename Ready>
+__device__ __forceinline__ bool lds_wait_until(Ready ready, uint32_t* lds_abort, Control* ctl, uint64_t& waited) {
+  if (ready()) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return true;
+  }
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  uint32_t polls = 0;
+  bool ok = true;
+  for (;;) {
+    if (ready()) break;
+    if ((++polls & 255u) == 0u) {
+      if (lds_load(lds_abort) != 0u || global_aborted(ctl)) {
+        ok = false;
+        break;
+      }
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) {
+        raise_timeout(ctl);
+        ok = false;
+        break;
+      }
+    }
+  }
+  waited += __builtin_amdgcn_s_memrealtime() - t0;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return ok;
+}
+
 // Wave-uniform wait until *p >= need.  Returns false if the launch is being aborted.
 template <bool check_global = true>
 __device__ __forceinline__ bool lds_wait_ge(const uint32_t* p, uint32_t need, uint32_t* lds_abort,

@@ -177,10 +177,7 @@ __device__ __forceinline__ bool unit_in_lds(uint64_t ready, int u) {
 // Waits until the C sub-chunk and the top unit that unit u reads are in LDS.
 template <typename T, int G, int R>
 __device__ __forceinline__ bool unit_wait(int u, Shared& sh, Control* ctl, uint64_t& waited) {
-  const uint32_t need_c = (uint32_t)((G * u) / kSub + 1);
-  const uint32_t need_t = (uint32_t)(u + 1);
-  return lds_wait_ge(&sh.ctr[0], need_c, &sh.abort, ctl, waited) &&
-         lds_wait_ge(&sh.ctr[1], need_t, &sh.abort, ctl, waited);
+  return lds_wait_until([&] { return __all(unit_in_lds<T, G, R>(load_ready(sh), u)); }, &sh.abort, ctl, waited);
 }
 
 // One unit of G steps.  'in' holds the first two groups of unit u (already read); the reads
