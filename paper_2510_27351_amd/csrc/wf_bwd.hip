@@ -100,6 +100,31 @@ __device__ __forceinline__ double sel_min(double a, double b) {
   return r;
 }
 
+// bits = 2 bits + (x < y): for 4-byte elements one compare into VCC and one add with VCC as
+// the carry in (the compiler's form takes a select, an or and a shift besides).
+__device__ __forceinline__ void sel_bit(uint32_t& bits, float x, float y) {
+  asm("v_cmp_lt_f32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc" : "+v"(bits) : "v"(x), "v"(y) : "vcc");
+}
+__device__ __forceinline__ void sel_bit(uint32_t& bits, double x, double y) { bits = bits + bits + (uint32_t)(x < y); }
+
+// One 4-step group's operands: C of the lane's row and the top row's values (a broadcast).
+template <typename T>
+struct SelGroup {
+  Vec4<T> c;
+  Vec4<T> t;
+};
+
+template <typename T>
+__device__ __forceinline__ void sel_load_group(const T* __restrict__ S, const T* __restrict__ Tr, int slot, int lane,
+                                               SelGroup<T>& r) {
+  using C = BCfg<T>;
+  r.c = *reinterpret_cast<const Vec4<T>*>(S + lane * C::PITCH + slot);
+  r.t = *reinterpret_cast<const Vec4<T>*>(Tr + slot);
+}
+
+// The compute wave.  Sub-chunk k (64 steps, 16 groups) starts once sub-chunks k and k+1 are
+// in LDS; each group's reads are issued two groups ahead of its steps, the last two groups
+// issuing the next sub-chunk's first two (left in 'P', the same registers every time).
 template <typename T>
 __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __restrict__ Tr, SelShared& sh,
                                             const SelArgs& a, int band, int Ks) {
@@ -113,54 +138,71 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
   T NW = (lane == 0 && band == 0) ? E::zero() : E::inf();  // virtual corner D[-1][-1] = 0
   uint32_t* out = a.sel;
   uint64_t waited = 0;
+  SelGroup<T> P[2];
   for (int k = 0; k < Ks; ++k) {
-    if (!lds_wait_ge(&sh.loaded, (uint32_t)(k + 1), &sh.abort, a.ctl, waited)) {
+    // LDS-only wait: a global load in this wave (the abort flag) would make the compiler wait
+    // for the wave's plane stores as well before reusing their registers.  A launch-wide
+    // abort reaches it through the wait's own time limit.
+    if (!lds_wait_ge<false>(&sh.loaded, (uint32_t)(k + 2 < Ks ? k + 2 : Ks), &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return;
     }
     const int base = (kSub * k) & C::MASK;
+    const int next = (kSub * (k + 1)) & C::MASK;  // past the last sub-chunk: read, not used
+    if (k == 0) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) sel_load_group<T>(S, Tr, 4 * p, lane, P[p]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    SelGroup<T> gr[18];
+    gr[0] = P[0];
+    gr[1] = P[1];
     uint32_t pl[3][2];
+    uint32_t pw = 0, pn = 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      // per step two bits, first step in the most significant bit: W strictly smaller
-      // than both others, N strictly smaller than NW
-      uint32_t pw = 0, pn = 0;
+    for (int g = 0; g < 16; ++g) {
+      if (g + 2 < 16)
+        sel_load_group<T>(S, Tr, base + 4 * (g + 2), lane, gr[g + 2]);
+      else
+        sel_load_group<T>(S, Tr, next + 4 * (g - 14), lane, P[g - 14]);
+      __builtin_amdgcn_sched_barrier(0);
+      // per step two bits, first step in the most significant bit: W strictly smaller than
+      // both others, N strictly smaller than NW
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        const int off = base + 32 * h + 4 * g;
-        const Vec4<T> cv = *reinterpret_cast<const Vec4<T>*>(S + lane * C::PITCH + off);
-        const Vec4<T> tv = *reinterpret_cast<const Vec4<T>*>(Tr + off);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T N = E::shr1(X, tv.v[q]);
-          const T m = sel_min(NW, N);
-          pn = pn + pn + (uint32_t)(N < NW);
-          pw = pw + pw + (uint32_t)(X < m);
-          X = E::add(cv.v[q], sel_min(m, X));
-          NW = N;
+      for (int q = 0; q < 4; ++q) {
+        const T N = E::shr1(X, gr[g].t.v[q]);
+        const T m = sel_min(NW, N);
+        sel_bit(pn, N, NW);
+        sel_bit(pw, X, m);
+        X = E::add(gr[g].c.v[q], sel_min(m, X));
+        NW = N;
+      }
+      if ((g & 7) == 7) {
+        const int h = g >> 3;
+        pw = __builtin_bitreverse32(pw);
+        pn = __builtin_bitreverse32(pn);
+        // predecessor: NW unless N is strictly smaller; W if strictly smaller than both
+        uint32_t pnw = ~pn & ~pw;
+        pn &= ~pw;
+        // clear the bits of cells outside the matrix (and of cell (0,0), which selects nothing)
+        const int t0 = kSub * k + 32 * h;
+        if (!(rows == kBand && t0 >= kBand - 1 && (int64_t)t0 + 32 <= n)) {
+          const int64_t lo = lane - (int64_t)t0, hi = n + lane - (int64_t)t0;  // valid steps [lo, hi)
+          const int a0 = (int)(lo < 0 ? 0 : (lo > 32 ? 32 : lo));
+          const int a1 = (int)(hi < 0 ? 0 : (hi > 32 ? 32 : hi));
+          uint64_t msk = a1 > a0 ? (((uint64_t)1 << a1) - 1) & ~(((uint64_t)1 << a0) - 1) : 0;
+          if (lane >= rows) msk = 0;
+          if (band == 0 && lane == 0 && t0 == 0) msk &= ~(uint64_t)1;
+          pw &= (uint32_t)msk;
+          pn &= (uint32_t)msk;
+          pnw &= (uint32_t)msk;
         }
+        pl[0][h] = pw;
+        pl[1][h] = pn;
+        pl[2][h] = pnw;
+        pw = 0;
+        pn = 0;
       }
-      pw = __builtin_bitreverse32(pw);
-      pn = __builtin_bitreverse32(pn);
-      // predecessor: NW unless N is strictly smaller; W if strictly smaller than both
-      uint32_t pnw = ~pn & ~pw;
-      pn &= ~pw;
-      // clear the bits of cells outside the matrix (and of cell (0,0), which selects nothing)
-      const int t0 = kSub * k + 32 * h;
-      if (!(rows == kBand && t0 >= kBand - 1 && (int64_t)t0 + 32 <= n)) {
-        const int64_t lo = lane - (int64_t)t0, hi = n + lane - (int64_t)t0;  // valid steps [lo, hi)
-        const int a0 = (int)(lo < 0 ? 0 : (lo > 32 ? 32 : lo));
-        const int a1 = (int)(hi < 0 ? 0 : (hi > 32 ? 32 : hi));
-        uint64_t msk = a1 > a0 ? (((uint64_t)1 << a1) - 1) & ~(((uint64_t)1 << a0) - 1) : 0;
-        if (lane >= rows) msk = 0;
-        if (band == 0 && lane == 0 && t0 == 0) msk &= ~(uint64_t)1;
-        pw &= (uint32_t)msk;
-        pn &= (uint32_t)msk;
-        pnw &= (uint32_t)msk;
-      }
-      pl[0][h] = pw;
-      pl[1][h] = pn;
-      pl[2][h] = pnw;
     }
     const v4i w0 = {(int)pl[0][0], (int)pl[0][1], (int)pl[1][0], (int)pl[1][1]};
     const v4i w1 = {(int)pl[2][0], (int)pl[2][1], 0, 0};
