@@ -25,8 +25,9 @@
 //     the receiving cell, as bytes in LDS.  Lane 63's inputs come from the band below, which
 //     publishes them (tagged 64-bit words, as in the forward sweep); the poller adds them to
 //     lane 63's upstream value before the compute wave reads it.
-// Waves of the reverse sweep: compute; loader (gD, factors); poller (values from the band
-// below); storer (gC); publisher (values for the band above).
+// Waves of the reverse sweep: compute; value loader (gD); factor loader (bit-planes ->
+// factors); poller (values from the band below); storer (gC); publisher (values for the
+// band above).
 #include "wf_common.h"
 
 namespace wf {
