@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <vector>
 
 #include "../../include/wf.h"
@@ -212,7 +213,6 @@ int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const
   rc = ensure_sel(ws, (size_t)nb * (size_t)Ks * 64 * 8);
   if (rc != WF_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
 
   SelArgs sa;
   sa.C = C;
@@ -224,6 +224,30 @@ int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const
     sa.top = static_cast<const char*>(D) + (size_t)63 * ldd * es;
     sa.ld_top = 64 * ldd;
   }
+  // With fewer than two bands per CU, each band is swept as two column pieces (two
+  // workgroups per CU), the second starting from a column of the forward table that the
+  // source holds: a block column of the checkpoint grid (a multiple of K) or any column of
+  // the saved table; the split is a multiple of 64 near n/2.
+  sa.split = 0;
+  sa.left = nullptr;
+  sa.ld_left = 0;
+  if (nb < 2 * (int64_t)ws->num_cus && n >= 1024) {
+    const int64_t K = ckpt_k > 0 ? ckpt_k : 64;
+    const int64_t L = K / std::gcd<int64_t>(K, 64) * 64;  // lcm(K, 64)
+    const int64_t c = (n / 2 + L / 2) / L * L;
+    if (c >= 256 && c <= n - 256) {
+      sa.split = c;
+      if (ckpt_k > 0) {  // block column q = c/K holds D[.][c-1]
+        sa.left = static_cast<const char*>(ckpt) + ((size_t)(nb - 1) * n + (size_t)(c / K - 1) * m) * es;
+        sa.ld_left = 1;
+      } else {
+        sa.left = static_cast<const char*>(D) + (size_t)(c - 1) * es;
+        sa.ld_left = ldd;
+      }
+    }
+  }
+  const int64_t items = sa.split > 0 ? 2 * nb : nb;
+  const int grid = (int)std::min<int64_t>(items, (sa.split > 0 ? 2 : 1) * (int64_t)ws->num_cus);
   sa.m = m;
   sa.n = n;
   sa.nb = (int32_t)nb;

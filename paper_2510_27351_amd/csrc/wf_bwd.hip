@@ -123,94 +123,143 @@ __device__ __forceinline__ void sel_load_group(const T* __restrict__ S, const T*
   r.t = *reinterpret_cast<const Vec4<T>*>(Tr + slot);
 }
 
-// The compute wave.  Sub-chunk k (64 steps, 16 groups) starts once sub-chunks k and k+1 are
-// in LDS; each group's reads are issued two groups ahead of its steps, the last two groups
-// issuing the next sub-chunk's first two (left in 'P', the same registers every time).
-template <typename T>
-__device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __restrict__ Tr, SelShared& sh,
-                                            const SelArgs& a, int band, int Ks) {
+// Sub-chunks [k0, k1) of the band that one piece of it sweeps: the whole band, or with a
+// column split at c = split (a multiple of 64) sub-chunks [0, c/64] for columns below c and
+// [c/64, Ks) for the rest.  Sub-chunk c/64 is swept by both; only the first stores it (its
+// cells of columns >= c are plain cells of the first piece's sweep too).
+struct SelPiece {
+  int k0, k1;
+  bool second;
+};
+__device__ __forceinline__ SelPiece sel_piece(const SelArgs& a, int piece, int Ks) {
+  const int ks = (int)(a.split / kSub);
+  if (a.split == 0) return {0, Ks, false};
+  return piece == 0 ? SelPiece{0, ks + 1, false} : SelPiece{ks, Ks, true};
+}
+
+// One sub-chunk of the compute wave (see sel_compute); ENTRY: the first sub-chunk of a
+// band's second piece, where each row takes its left value and nothing is stored.
+template <typename T, bool ENTRY>
+__device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __restrict__ Tr, const SelArgs& a, int band,
+                                        int Ks, int k, int rows, int64_t n, T& X, T& NW, T left,
+                                        SelGroup<T> (&P)[2]) {
   using C = BCfg<T>;
   using E = typename C::E;
   typedef int v4i __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
-  const int64_t n = opaque(a.n);
-  const int rows = (int)(a.m - (int64_t)band * kBand < kBand ? a.m - (int64_t)band * kBand : kBand);
-  T X = E::inf();
-  T NW = (lane == 0 && band == 0) ? E::zero() : E::inf();  // virtual corner D[-1][-1] = 0
   uint32_t* out = a.sel;
-  uint64_t waited = 0;
-  SelGroup<T> P[2];
-  for (int k = 0; k < Ks; ++k) {
-    // LDS-only wait: a global load in this wave (the abort flag) would make the compiler wait
-    // for the wave's plane stores as well before reusing their registers.  A launch-wide
-    // abort reaches it through the wait's own time limit.
-    if (!lds_wait_ge<false>(&sh.loaded, (uint32_t)(k + 2 < Ks ? k + 2 : Ks), &sh.abort, a.ctl, waited)) {
-      sh.abort = 1u;
-      return;
-    }
-    const int base = (kSub * k) & C::MASK;
-    const int next = (kSub * (k + 1)) & C::MASK;  // past the last sub-chunk: read, not used
-    if (k == 0) {
+  const int base = (kSub * k) & C::MASK;
+  const int next = (kSub * (k + 1)) & C::MASK;  // past the last sub-chunk: read, not used
+  __builtin_amdgcn_sched_barrier(0);
+  SelGroup<T> gr[18];
+  gr[0] = P[0];
+  gr[1] = P[1];
+  uint32_t pl[3][2];
+  uint32_t pw = 0, pn = 0;
 #pragma unroll
-      for (int p = 0; p < 2; ++p) sel_load_group<T>(S, Tr, 4 * p, lane, P[p]);
-    }
+  for (int g = 0; g < 16; ++g) {
+    if (g + 2 < 16)
+      sel_load_group<T>(S, Tr, base + 4 * (g + 2), lane, gr[g + 2]);
+    else
+      sel_load_group<T>(S, Tr, next + 4 * (g - 14), lane, P[g - 14]);
     __builtin_amdgcn_sched_barrier(0);
-    SelGroup<T> gr[18];
-    gr[0] = P[0];
-    gr[1] = P[1];
-    uint32_t pl[3][2];
-    uint32_t pw = 0, pn = 0;
+    // per step two bits, first step in the most significant bit: W strictly smaller than
+    // both others, N strictly smaller than NW
 #pragma unroll
-    for (int g = 0; g < 16; ++g) {
-      if (g + 2 < 16)
-        sel_load_group<T>(S, Tr, base + 4 * (g + 2), lane, gr[g + 2]);
-      else
-        sel_load_group<T>(S, Tr, next + 4 * (g - 14), lane, P[g - 14]);
-      __builtin_amdgcn_sched_barrier(0);
-      // per step two bits, first step in the most significant bit: W strictly smaller than
-      // both others, N strictly smaller than NW
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T N = E::shr1(X, gr[g].t.v[q]);
-        const T m = sel_min(NW, N);
-        sel_bit(pn, N, NW);
-        sel_bit(pw, X, m);
-        X = E::add(gr[g].c.v[q], sel_min(m, X));
-        NW = N;
-      }
-      if ((g & 7) == 7) {
-        const int h = g >> 3;
-        pw = __builtin_bitreverse32(pw);
-        pn = __builtin_bitreverse32(pn);
-        // predecessor: NW unless N is strictly smaller; W if strictly smaller than both
-        uint32_t pnw = ~pn & ~pw;
-        pn &= ~pw;
-        // clear the bits of cells outside the matrix (and of cell (0,0), which selects nothing)
-        const int t0 = kSub * k + 32 * h;
-        if (!(rows == kBand && t0 >= kBand - 1 && (int64_t)t0 + 32 <= n)) {
-          const int64_t lo = lane - (int64_t)t0, hi = n + lane - (int64_t)t0;  // valid steps [lo, hi)
-          const int a0 = (int)(lo < 0 ? 0 : (lo > 32 ? 32 : lo));
-          const int a1 = (int)(hi < 0 ? 0 : (hi > 32 ? 32 : hi));
-          uint64_t msk = a1 > a0 ? (((uint64_t)1 << a1) - 1) & ~(((uint64_t)1 << a0) - 1) : 0;
-          if (lane >= rows) msk = 0;
-          if (band == 0 && lane == 0 && t0 == 0) msk &= ~(uint64_t)1;
-          pw &= (uint32_t)msk;
-          pn &= (uint32_t)msk;
-          pnw &= (uint32_t)msk;
-        }
-        pl[0][h] = pw;
-        pl[1][h] = pn;
-        pl[2][h] = pnw;
-        pw = 0;
-        pn = 0;
-      }
+    for (int q = 0; q < 4; ++q) {
+      const T N = E::shr1(X, gr[g].t.v[q]);
+      const T m = sel_min(NW, N);
+      sel_bit(pn, N, NW);
+      sel_bit(pw, X, m);
+      X = E::add(gr[g].c.v[q], sel_min(m, X));
+      NW = N;
+      if (ENTRY && 4 * g + q == lane - 1) X = left;
     }
+    if ((g & 7) == 7) {
+      const int h = g >> 3;
+      pw = __builtin_bitreverse32(pw);
+      pn = __builtin_bitreverse32(pn);
+      // predecessor: NW unless N is strictly smaller; W if strictly smaller than both
+      uint32_t pnw = ~pn & ~pw;
+      pn &= ~pw;
+      // clear the bits of cells outside the matrix (and of cell (0,0), which selects nothing)
+      const int t0 = kSub * k + 32 * h;
+      if (!(rows == kBand && t0 >= kBand - 1 && (int64_t)t0 + 32 <= n)) {
+        const int64_t lo = lane - (int64_t)t0, hi = n + lane - (int64_t)t0;  // valid steps [lo, hi)
+        const int a0 = (int)(lo < 0 ? 0 : (lo > 32 ? 32 : lo));
+        const int a1 = (int)(hi < 0 ? 0 : (hi > 32 ? 32 : hi));
+        uint64_t msk = a1 > a0 ? (((uint64_t)1 << a1) - 1) & ~(((uint64_t)1 << a0) - 1) : 0;
+        if (lane >= rows) msk = 0;
+        if (band == 0 && lane == 0 && t0 == 0) msk &= ~(uint64_t)1;
+        pw &= (uint32_t)msk;
+        pn &= (uint32_t)msk;
+        pnw &= (uint32_t)msk;
+      }
+      pl[0][h] = pw;
+      pl[1][h] = pn;
+      pl[2][h] = pnw;
+      pw = 0;
+      pn = 0;
+    }
+  }
+  if (!ENTRY) {
     const v4i w0 = {(int)pl[0][0], (int)pl[0][1], (int)pl[1][0], (int)pl[1][1]};
     const v4i w1 = {(int)pl[2][0], (int)pl[2][1], 0, 0};
     v4i* dst = reinterpret_cast<v4i*>(out + sel_index(band, Ks, k, lane));
     __builtin_nontemporal_store(w0, dst);
     __builtin_nontemporal_store(w1, dst + 1);
-    lds_signal(&sh.steps, (uint32_t)(kSub * (k + 1)));
+  }
+}
+
+// The compute wave.  Sub-chunk k (64 steps, 16 groups) starts once sub-chunks k and k+1 are
+// in LDS; each group's reads are issued two groups ahead of its steps, the last two groups
+// issuing the next sub-chunk's first two (left in 'P', the same registers every time).
+// The second piece of a split band starts at slot 'split' (column split - r for row r):
+// row r's state enters as column split-1 of the forward table, which the wave sets at step
+// r-1 (row 0 before the first step, its NW from the row above); the cells before it are
+// none of this piece's and their selections are not stored.
+template <typename T>
+__device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __restrict__ Tr, SelShared& sh,
+                                            const SelArgs& a, int band, int Ks, SelPiece pc) {
+  using C = BCfg<T>;
+  using E = typename C::E;
+  const int lane = threadIdx.x & 63;
+  const int64_t n = opaque(a.n);
+  const int rows = (int)(a.m - (int64_t)band * kBand < kBand ? a.m - (int64_t)band * kBand : kBand);
+  T X = E::inf();
+  T NW = (lane == 0 && band == 0) ? E::zero() : E::inf();  // virtual corner D[-1][-1] = 0
+  T left = E::inf();
+  if (pc.second) {
+    const T* lp = static_cast<const T*>(a.left);
+    const int64_t c = opaque(a.split) - 1;
+    if (lane < rows) left = lp[((int64_t)band * kBand + lane) * a.ld_left];
+    if (lane == 0) {
+      X = left;
+      NW = band > 0 ? static_cast<const T*>(a.top)[(int64_t)(band - 1) * a.ld_top + c] : E::inf();
+    }
+  }
+  uint64_t waited = 0;
+  SelGroup<T> P[2];
+  const int nk = pc.k1 - pc.k0;
+  for (int k = pc.k0; k < pc.k1; ++k) {
+    const int kl = k - pc.k0;  // sub-chunks counted from the piece's first
+    // LDS-only wait: a global load in this wave (the abort flag) would make the compiler wait
+    // for the wave's plane stores as well before reusing their registers.  A launch-wide
+    // abort reaches it through the wait's own time limit.
+    if (!lds_wait_ge<false>(&sh.loaded, (uint32_t)(kl + 2 < nk ? kl + 2 : nk), &sh.abort, a.ctl, waited)) {
+      sh.abort = 1u;
+      return;
+    }
+    if (k == pc.k0) {
+      const int base = (kSub * k) & C::MASK;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) sel_load_group<T>(S, Tr, base + 4 * p, lane, P[p]);
+    }
+    if (pc.second && k == pc.k0)
+      sel_sub<T, true>(S, Tr, a, band, Ks, k, rows, n, X, NW, left, P);
+    else
+      sel_sub<T, false>(S, Tr, a, band, Ks, k, rows, n, X, NW, left, P);
+    lds_signal(&sh.steps, (uint32_t)(kSub * (kl + 1)));
   }
 }
 
@@ -273,7 +322,8 @@ __device__ __forceinline__ void sel_store_sub(T* S, T* Tr, const Vec4<T> (&x)[16
 }
 
 template <typename T>
-__device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const SelArgs& a, int band, int Ks) {
+__device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const SelArgs& a, int band, int Ks,
+                                           SelPiece pc) {
   using C = BCfg<T>;
   constexpr int PF = SelPF<T>::PF;
   const int64_t ldc = opaque(a.ldc), n = opaque(a.n), m = opaque(a.m);
@@ -289,36 +339,37 @@ __device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const Sel
   uint64_t waited = 0;
   Vec4<T> buf[PF][16];
   T tv[PF];
+  const int k0 = pc.k0, k1 = pc.k1;
   // The loads of sub-chunk k+PF are issued right after sub-chunk k is stored, unconditionally
-  // (clamped to the last sub-chunk), so that PF sub-chunks are in flight at every wait.
+  // (clamped to the piece's last sub-chunk), so that PF sub-chunks are in flight at every wait.
 #pragma unroll
-  for (int p = 0; p < PF; ++p) sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, p < Ks ? p : Ks - 1);
+  for (int p = 0; p < PF; ++p) sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, k0 + p < k1 ? k0 + p : k1 - 1);
   auto store = [&](int p, int k) -> bool {
-    // sub-chunk k reuses the ring slots of sub-chunk k - RING/64
-    const int older = k - C::RING / kSub;
+    // sub-chunk k reuses the ring slots of sub-chunk k - RING/64 (counted from the piece's first)
+    const int older = k - k0 - C::RING / kSub;
     if (older >= 0 &&
         !lds_wait_ge<false>(&sh.steps, (uint32_t)(kSub * (older + 1)), &sh.abort, a.ctl, waited)) {
       sh.abort = 1u;
       return false;
     }
     sel_store_sub<T>(S, Tr, buf[p], tv[p], has_top, k, rows, n);
-    lds_publish(&sh.loaded, (uint32_t)(k + 1));
+    lds_publish(&sh.loaded, (uint32_t)(k - k0 + 1));
     return true;
   };
   // Whole groups of PF sub-chunks carry no condition around the stores, which keeps the
   // compiler's wait counts at PF - 1 sub-chunks in flight; the last partial group follows.
-  int k0 = 0;
-  for (; k0 + PF <= Ks; k0 += PF) {
+  int kk = k0;
+  for (; kk + PF <= k1; kk += PF) {
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-      const int k = k0 + p;
+      const int k = kk + p;
       if (!store(p, k)) return;
-      sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, k + PF < Ks ? k + PF : Ks - 1);
+      sel_load_sub<T>(buf[p], tv[p], rsrc, ldc, top, n, k + PF < k1 ? k + PF : k1 - 1);
     }
   }
 #pragma unroll
   for (int p = 0; p < PF; ++p)
-    if (k0 + p < Ks && !store(p, k0 + p)) return;
+    if (kk + p < k1 && !store(p, kk + p)) return;
 }
 
 template <typename T>
@@ -339,12 +390,16 @@ __global__ __launch_bounds__(128, 1) void sel_kernel(SelArgs a) {
       sh.steps = 0u;
     }
     claim_next(ctl, &sh.item, &sh.abort);
-    const int band = (int)sh.item;
-    if (band >= a.nb || sh.abort != 0u) break;
+    // work items: bands, or (band, piece) pairs of split bands
+    const int pieces = a.split > 0 ? 2 : 1;
+    const int item = (int)sh.item;
+    if (item >= a.nb * pieces || sh.abort != 0u) break;
+    const int band = item / pieces;
+    const SelPiece pc = sel_piece(a, item % pieces, Ks);
     if (threadIdx.x < 64)
-      sel_compute<T>(S, Tr, sh, a, band, Ks);
+      sel_compute<T>(S, Tr, sh, a, band, Ks, pc);
     else
-      sel_loader<T>(S, Tr, sh, a, band, Ks);
+      sel_loader<T>(S, Tr, sh, a, band, Ks, pc);
     __syncthreads();
   }
   finish_launch(ctl, epoch);

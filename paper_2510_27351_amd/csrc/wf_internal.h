@@ -71,6 +71,12 @@ struct SelArgs {
   int32_t Q;          // sel words per lane per band
   uint32_t* sel;
   Control* ctl;
+  // Column split (split > 0): each band is swept as two pieces, columns [0, split) and
+  // [split, n), split a multiple of 64; the second starts from column split-1 of the forward
+  // table, D[i][split-1] at left + i * ld_left.
+  int64_t split;
+  const void* left;
+  int64_t ld_left;
 };
 
 // Arguments of the reverse adjoint sweep (second half): bands of 64 rows from the bottom

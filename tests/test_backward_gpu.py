@@ -158,6 +158,27 @@ def _padded(D):
     return P
 
 
+@pytest.mark.parametrize("shape", [(130, 1500), (64, 2048), (257, 1100), (1, 1024)])
+@pytest.mark.parametrize("source,ckpt_k", [("table", 64), ("ckpt", 64), ("ckpt", 192)])
+def test_f32_adjoint_split_selection(oracle_mod, shape, source, ckpt_k):
+    """n >= 1024 with few bands: the selection recompute sweeps each band as two column
+    pieces, the second entering from a column of the table or of the checkpoint grid
+    (a multiple of lcm(K, 64) near n/2); the adjoint stays bitwise equal to the oracle's."""
+    m, n = shape
+    C = inputs.normal_clipped(m, n, seed=m * 7 + n)
+    got = gpu_grad(C, None, 1.0, source, ckpt_k=ckpt_k)
+    ref = oracle_grad(oracle_mod, C, None, 1.0, "f32")
+    assert torch.equal(got, ref)
+
+
+def test_f64_adjoint_split_selection(oracle_mod):
+    C = inputs.normal_clipped(150, 1300, seed=5).double()
+    gD = inputs.normal_clipped(150, 1300, seed=6).double()
+    got = gpu_grad(C, gD, 0.5, "ckpt", ckpt_k=64)
+    ref = oracle_grad(oracle_mod, C, gD, 0.5, "f64")
+    assert torch.equal(got, ref)
+
+
 def test_adjoint_4096_f32(oracle_mod):
     """The 4096 x 4096 workload.
     - bitwise equal to the float32 oracle's adjoint;
