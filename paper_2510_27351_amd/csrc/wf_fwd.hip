@@ -463,25 +463,33 @@ __device__ __forceinline__ void top_band(const T* S, T* Tr, Shared& sh, const Fw
     };
     T val;
     int k;
-    issue(xa);
-    for (;;) {
-      issue(xb);
-      if ((k = complete(xa)) > 0) {
-        val = value(xa);
-        break;
-      }
-      if (!pause()) {
-        sh.abort = 1u;
-        return;
-      }
+    if (band == 0 || j0 >= n) {
+      // nothing to fetch (the first band's top row is virtual, and so are the columns past
+      // the matrix): +inf without a round trip through memory, so that the first band --
+      // whose pace every later band follows -- never waits for its poller
+      k = (int)(kSub / G) < Ut - u ? (int)(kSub / G) : Ut - u;
+      val = E::inf();
+    } else {
       issue(xa);
-      if ((k = complete(xb)) > 0) {
-        val = value(xb);
-        break;
-      }
-      if (!pause()) {
-        sh.abort = 1u;
-        return;
+      for (;;) {
+        issue(xb);
+        if ((k = complete(xa)) > 0) {
+          val = value(xa);
+          break;
+        }
+        if (!pause()) {
+          sh.abort = 1u;
+          return;
+        }
+        issue(xa);
+        if ((k = complete(xb)) > 0) {
+          val = value(xb);
+          break;
+        }
+        if (!pause()) {
+          sh.abort = 1u;
+          return;
+        }
       }
     }
     if (polls != 0u) {
@@ -538,8 +546,8 @@ __device__ __forceinline__ void store_sub(const T* S, __amdgpu_buffer_rsrc_t drs
   }
   // Edge sub-chunk (first, last, or a partial band): the same 16 LDS reads first, then per
   // vector one 16-byte store if its four cells lie inside the matrix, else a store per cell
-  // that does.
-#pragma unroll
+  // that does (one sub-band at a time: both at once would not fit the registers).
+#pragma unroll 1
   for (int h = 0; h < R; ++h) {
     Vec4<T> v[16];
 #pragma unroll
