@@ -239,7 +239,8 @@ def main():
         "config": {"workload": f"single {m}x{n} float32, normal(0,1) clipped to [-4,4], seed 2; step = "
                                f"forward (table, score, checkpoint grid K={CKPT_K}) + adjoint of the score "
                                "from the checkpoint grid (selection recompute + reverse sweep)",
-                   "m": m, "n": n, "ckpt_k": CKPT_K},
+                   "m": m, "n": n, "ckpt_k": CKPT_K,
+                   "tile_forward": wf.predict_tile(m, n), "tile_reverse": wf.predict_tile(m, n, reverse=True)},
         "fwd": {"ms": fwd_ms, "cells_per_s": cells / (fwd_ms * 1e-3),
                 "effective_GBps": eff(3 * cells * es, fwd_ms),
                 "effective_pct_peak": 100 * eff(3 * cells * es, fwd_ms) / PEAK_HBM_GBPS},

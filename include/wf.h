@@ -170,6 +170,17 @@ void wf_plan_destroy(wf_plan* plan);
 int wf_set_tile(int32_t tile);
 
 /*
+ * The automatic choice: the tile G (16, 32 or 64) that wf_forward (reverse = 0) or
+ * wf_reverse / wf_backward (reverse = 1) use for an m x n instance, by nearest-neighbour
+ * classification (k = 1, as the paper's kNN heuristic for its sub-system size in the
+ * section "Building a heuristic for the optimum sub-system size"): the fastest tile of the
+ * closest shape, in (log2 m, log2 n), of a table of shapes timed on MI355X (float32; ties
+ * go to the earlier table row).  Host-only, needs no device.  WF_E_ARG if m < 1, n < 1 or
+ * reverse is not 0 or 1.
+ */
+int32_t wf_tile_predict(int64_t m, int64_t n, int32_t reverse);
+
+/*
  * Tracing (for profiling the pipeline, off by default).  wf_trace_enable(B) allocates a
  * device buffer of B records on the current device; later forward calls and reverse sweeps
  * of wf_backward on that device whose band count is <= B fill record b for band b (a later

@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import WfError  # noqa: F401
 
-__all__ = ["forward", "backward", "sweep", "WfFunction", "Plan", "ckpt_elems", "set_tile",
+__all__ = ["forward", "backward", "sweep", "WfFunction", "Plan", "ckpt_elems", "set_tile", "predict_tile",
            "last_async_error", "WfError", "BAND"]
 
 BAND = 64  # rows per band of the device sweep (= wavefront size)
@@ -256,6 +256,14 @@ class Plan:
 
 def set_tile(tile: int) -> None:
     _lib.check(_lib.load().wf_set_tile(tile), "wf_set_tile")
+
+
+def predict_tile(m: int, n: int, reverse: bool = False) -> int:
+    """The tile G the library picks for an m x n instance when none is forced: the fastest
+    tile of the nearest shape (in log2 m, log2 n) of its MI355X timing table (wf_tile_predict)."""
+    t = _lib.load().wf_tile_predict(m, n, 1 if reverse else 0)
+    _lib.check(t if t < 0 else 0, "wf_tile_predict")
+    return t
 
 
 def last_async_error(device=None) -> None:

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -86,18 +87,15 @@ int words_per_elem(int dtype) { return dtype == WF_F64 ? 2 : 1; }
 
 namespace {
 
-// Tile width used when the caller has not forced one.
-// Handoff granularity G.  The forward sweep is fastest with 64 on wide matrices; the
-// reverse sweep, whose compute wave is slower per step, with 32 (measured at 16384 x 16384
-// on MI355X).
+// Tile of the single-instance sweeps for a shape: the caller's override (wf_set_tile, then
+// WF_TILE), else the nearest-neighbour prediction from the tiles measured on MI355X.
 int choose_tile(int64_t m, int64_t n, bool reverse) {
   if (g_tile_override) return g_tile_override;
   if (const char* s = std::getenv("WF_TILE")) {
     int t = std::atoi(s);
     if (t == 16 || t == 32 || t == 64) return t;
   }
-  (void)m;
-  return n >= 1024 && !reverse ? 64 : 32;
+  return wf_tile_predict(m, n, reverse ? 1 : 0);
 }
 
 int64_t nbands(int64_t m) { return (m + kBand - 1) / kBand; }
@@ -121,6 +119,37 @@ const char* wf_error_string(int code) {
     case WF_E_TIMEOUT: return "device-side wait timed out";
     default: return "unknown error";
   }
+}
+
+// The fastest tile G of the forward sweep (table, score, checkpoint grid K = 64) and of the
+// reverse sweep (timed behind the selection recompute, where it always runs) on MI355X for a
+// grid of shapes, float32 (python -m paper_2510_27351_amd.tile_sweep: best of 3 rounds of 10
+// calls per tile).  The training set of the nearest-neighbour rule below.
+struct TileObs {
+  int64_t m, n;
+  int32_t fwd, rev;
+};
+static const TileObs kTileTable[] = {
+    {256, 256, 64, 32},     {256, 1024, 64, 64},     {256, 4096, 64, 64},     {256, 16384, 64, 64},
+    {1024, 256, 32, 32},    {1024, 1024, 64, 32},    {1024, 4096, 64, 64},    {1024, 16384, 64, 64},
+    {4096, 256, 32, 32},    {4096, 1024, 32, 32},    {4096, 4096, 64, 32},    {4096, 16384, 64, 64},
+    {16384, 256, 32, 32},   {16384, 1024, 32, 32},   {16384, 4096, 64, 32},   {16384, 16384, 64, 32},
+};
+
+int32_t wf_tile_predict(int64_t m, int64_t n, int32_t reverse) {
+  if (m < 1 || n < 1 || (reverse != 0 && reverse != 1)) return WF_E_ARG;
+  const double lm = std::log2((double)m), ln = std::log2((double)n);
+  int best = 0;
+  double best_d = INFINITY;
+  for (int i = 0; i < (int)(sizeof(kTileTable) / sizeof(kTileTable[0])); ++i) {
+    const double dm = lm - std::log2((double)kTileTable[i].m), dn = ln - std::log2((double)kTileTable[i].n);
+    const double d = dm * dm + dn * dn;
+    if (d < best_d) {  // strictly nearer: ties go to the earlier row
+      best = i;
+      best_d = d;
+    }
+  }
+  return reverse ? kTileTable[best].rev : kTileTable[best].fwd;
 }
 
 int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k) {
