@@ -34,6 +34,20 @@ def predict(train_x, train_y, x):
     return np.array(out)
 
 
+# The paper's observed trend of the optimum sub-system size m over the system size N (section
+# "Observations on the optimum sub-system size"): m is constant on each interval of N, the
+# interval closed at its upper end.  Pairs (upper end of N, m).
+_INTERVALS = ((4.5e3, 4), (2.5e4, 8), (5e4, 16), (7.5e4, 20), (1e7, 32), (1e8, 64))
+
+
+def interval_rule(N) -> int:
+    """The optimum m that the observed trend assigns to a system size N (0 < N <= 1e8)."""
+    for upper, m in _INTERVALS:
+        if N <= upper:
+            return m
+    raise ValueError("N beyond the sizes the trend covers")
+
+
 def null_accuracy(y) -> float:
     """Accuracy of always predicting the most frequent label."""
     _, counts = np.unique(np.asarray(y), return_counts=True)
