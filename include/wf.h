@@ -171,14 +171,17 @@ int wf_set_tile(int32_t tile);
 
 /*
  * The automatic choice: the tile G (16, 32 or 64) that wf_forward (reverse = 0) or
- * wf_reverse / wf_backward (reverse = 1) use for an m x n instance, by nearest-neighbour
- * classification (k = 1, as the paper's kNN heuristic for its sub-system size in the
- * section "Building a heuristic for the optimum sub-system size"): the fastest tile of the
- * closest shape, in (log2 m, log2 n), of a table of shapes timed on MI355X (float32; ties
- * go to the earlier table row).  Host-only, needs no device.  WF_E_ARG if m < 1, n < 1 or
- * reverse is not 0 or 1.
+ * wf_reverse / wf_backward (reverse = 1) use for an m x n instance of element type dtype,
+ * by nearest-neighbour classification (k = 1, as the paper's kNN heuristic for its
+ * sub-system size in the section "Building a heuristic for the optimum sub-system size"):
+ * the fastest tile of the closest shape, in (log2 m, log2 n), of a table of shapes timed on
+ * MI355X in float32 and in float64 (ties go to the earlier table row; WF_I32 uses the
+ * float32 forward column).  Host-only, needs no device.  Returns the tile, or an error code
+ * (all error codes are below 16): WF_E_ARG if dtype is not a wf_dtype, m < 1, n < 1 or
+ * reverse is not 0 or 1; WF_E_UNSUPPORTED for WF_I32 with reverse = 1 (there is no integer
+ * adjoint).
  */
-int32_t wf_tile_predict(int64_t m, int64_t n, int32_t reverse);
+int32_t wf_tile_predict(int32_t dtype, int64_t m, int64_t n, int32_t reverse);
 
 /*
  * Tracing (for profiling the pipeline, off by default).  wf_trace_enable(B) allocates a

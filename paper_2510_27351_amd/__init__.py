@@ -258,11 +258,14 @@ def set_tile(tile: int) -> None:
     _lib.check(_lib.load().wf_set_tile(tile), "wf_set_tile")
 
 
-def predict_tile(m: int, n: int, reverse: bool = False) -> int:
+def predict_tile(m: int, n: int, reverse: bool = False, dtype: torch.dtype = torch.float32) -> int:
     """The tile G the library picks for an m x n instance when none is forced: the fastest
-    tile of the nearest shape (in log2 m, log2 n) of its MI355X timing table (wf_tile_predict)."""
-    t = _lib.load().wf_tile_predict(m, n, 1 if reverse else 0)
-    _lib.check(t if t < 0 else 0, "wf_tile_predict")
+    tile of the nearest shape (in log2 m, log2 n) of its MI355X timing table for that element
+    type (wf_tile_predict)."""
+    code = {torch.float32: _lib.WF_F32, torch.float64: _lib.WF_F64, torch.int32: _lib.WF_I32}.get(dtype, -1)
+    t = _lib.load().wf_tile_predict(code, m, n, 1 if reverse else 0)
+    if t not in (16, 32, 64):
+        raise _lib.WfError(t, "wf_tile_predict")
     return t
 
 

@@ -55,7 +55,7 @@ def load():
     lib.wf_ckpt_elems.restype = i64
     lib.wf_set_tile.argtypes = [i32]
     lib.wf_set_tile.restype = ctypes.c_int
-    lib.wf_tile_predict.argtypes = [i64, i64, i32]
+    lib.wf_tile_predict.argtypes = [i32, i64, i64, i32]
     lib.wf_tile_predict.restype = i32
     lib.wf_last_async_error.argtypes = [p]
     lib.wf_last_async_error.restype = ctypes.c_int

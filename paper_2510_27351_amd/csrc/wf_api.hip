@@ -89,13 +89,14 @@ namespace {
 
 // Tile of the single-instance sweeps for a shape: the caller's override (wf_set_tile, then
 // WF_TILE), else the nearest-neighbour prediction from the tiles measured on MI355X.
-int choose_tile(int64_t m, int64_t n, bool reverse) {
+int choose_tile(int dtype, int64_t m, int64_t n, bool reverse) {
   if (g_tile_override) return g_tile_override;
   if (const char* s = std::getenv("WF_TILE")) {
     int t = std::atoi(s);
     if (t == 16 || t == 32 || t == 64) return t;
   }
-  return wf_tile_predict(m, n, reverse ? 1 : 0);
+  // the callers have validated dtype, m and n, so this is a tile, never an error code
+  return wf_tile_predict(dtype, m, n, reverse ? 1 : 0);
 }
 
 int64_t nbands(int64_t m) { return (m + kBand - 1) / kBand; }
@@ -123,21 +124,27 @@ const char* wf_error_string(int code) {
 
 // The fastest tile G of the forward sweep (table, score, checkpoint grid K = 64) and of the
 // reverse sweep (timed behind the selection recompute, where it always runs) on MI355X for a
-// grid of shapes, float32 (python -m paper_2510_27351_amd.tile_sweep: best of 3 rounds of 10
-// calls per tile).  The training set of the nearest-neighbour rule below.
+// grid of shapes, in float32 and in float64 (python -m paper_2510_27351_amd.tile_sweep
+// [--dtype f64]: best of 3 rounds of 10 calls per tile).  The training set of the
+// nearest-neighbour rule below; the two element types get a column pair each, since the
+// float32 choices lose up to 18% when reused for float64.
 struct TileObs {
   int64_t m, n;
-  int32_t fwd, rev;
+  int32_t fwd32, rev32, fwd64, rev64;
 };
 static const TileObs kTileTable[] = {
-    {256, 256, 64, 32},     {256, 1024, 64, 64},     {256, 4096, 64, 64},     {256, 16384, 64, 64},
-    {1024, 256, 32, 32},    {1024, 1024, 64, 32},    {1024, 4096, 64, 64},    {1024, 16384, 64, 64},
-    {4096, 256, 32, 32},    {4096, 1024, 32, 32},    {4096, 4096, 64, 32},    {4096, 16384, 64, 64},
-    {16384, 256, 32, 32},   {16384, 1024, 32, 32},   {16384, 4096, 64, 32},   {16384, 16384, 64, 32},
+    {256, 256, 64, 32, 32, 16},       {256, 1024, 64, 64, 64, 64},     {256, 4096, 64, 64, 64, 64},
+    {256, 16384, 64, 64, 64, 64},     {1024, 256, 32, 32, 32, 16},     {1024, 1024, 64, 32, 64, 64},
+    {1024, 4096, 64, 64, 64, 64},     {1024, 16384, 64, 64, 64, 64},   {4096, 256, 32, 32, 32, 16},
+    {4096, 1024, 32, 32, 32, 16},     {4096, 4096, 64, 32, 32, 64},    {4096, 16384, 64, 64, 64, 64},
+    {16384, 256, 32, 32, 32, 16},     {16384, 1024, 32, 32, 32, 16},   {16384, 4096, 64, 32, 32, 16},
+    {16384, 16384, 64, 32, 64, 64},
 };
 
-int32_t wf_tile_predict(int64_t m, int64_t n, int32_t reverse) {
+int32_t wf_tile_predict(int32_t dtype, int64_t m, int64_t n, int32_t reverse) {
+  if (dtype != WF_F32 && dtype != WF_F64 && dtype != WF_I32) return WF_E_ARG;
   if (m < 1 || n < 1 || (reverse != 0 && reverse != 1)) return WF_E_ARG;
+  if (dtype == WF_I32 && reverse) return WF_E_UNSUPPORTED;
   const double lm = std::log2((double)m), ln = std::log2((double)n);
   int best = 0;
   double best_d = INFINITY;
@@ -149,7 +156,9 @@ int32_t wf_tile_predict(int64_t m, int64_t n, int32_t reverse) {
       best_d = d;
     }
   }
-  return reverse ? kTileTable[best].rev : kTileTable[best].fwd;
+  const TileObs& o = kTileTable[best];
+  if (dtype == WF_F64) return reverse ? o.rev64 : o.fwd64;
+  return reverse ? o.rev32 : o.fwd32;  // int32 has float32's element size and no reverse sweep
 }
 
 int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k) {
@@ -207,7 +216,7 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
   a.bnd = ws->bnd;
   a.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
   const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
-  const int tile = choose_tile(m, n, false);
+  const int tile = choose_tile(dtype, m, n, false);
   hipError_t e = launch_forward(dtype, tile, a, grid, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
@@ -328,7 +337,7 @@ int wf_reverse(int dtype, int64_t m, int64_t n, const void* g_score, const void*
   aa.ctl = ws->ctl;
   aa.bnd = ws->bnd;
   aa.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
-  hipError_t e = launch_adjoint(dtype, choose_tile(m, n, true), aa, grid, st);
+  hipError_t e = launch_adjoint(dtype, choose_tile(dtype, m, n, true), aa, grid, st);
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
 

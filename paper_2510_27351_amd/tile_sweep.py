@@ -1,6 +1,6 @@
 """Times the single-instance sweeps at every tile G in {16, 32, 64} over a grid of shapes.
 
-    python -m paper_2510_27351_amd.tile_sweep [--sizes 256,1024,4096,16384] [--reps 10] [--rounds 3]
+    python -m paper_2510_27351_amd.tile_sweep [--sizes 256,1024,4096,16384] [--reps 10] [--rounds 3] [--dtype f32|f64]
 
 For each (m, n) of the grid it prints, per tile, the time of the forward (table, score,
 checkpoint grid K=64), of the selection recompute alone and of the adjoint (selection
@@ -11,7 +11,7 @@ timed behind it because that is where it always runs (the selections it reads we
 written).  The table is the training set of the library's tile predictor (wf_tile_predict:
 the tile of the nearest timed shape in (log2 m, log2 n)); after a change to the kernels,
 sweep again and replace the table in the library and its copy in the tests.  Inputs are
-normal(0,1) clipped to [-4,4], float32, seeded per shape.
+normal(0,1) clipped to [-4,4], float32 (or float64), seeded per shape.
 """
 from __future__ import annotations
 
@@ -38,12 +38,12 @@ def _time(fn, reps: int) -> float:
     return start.elapsed_time(end) / reps
 
 
-def sweep(sizes, reps: int, rounds: int):
+def sweep(sizes, reps: int, rounds: int, dtype=torch.float32):
     rows = []
-    one = torch.ones((), device="cuda")
+    one = torch.ones((), device="cuda", dtype=dtype)
     for m in sizes:
         for n in sizes:
-            C = inputs.normal_clipped(m, n, seed=m * 31 + n).cuda()
+            C = inputs.normal_clipped(m, n, seed=m * 31 + n, dtype=dtype).cuda()
             D = torch.empty_like(C)
             gC = torch.empty_like(C)
             times = {t: (float("inf"),) * 3 for t in TILES}
@@ -61,7 +61,7 @@ def sweep(sizes, reps: int, rounds: int):
 
                         def adj():
                             wf.select(C, ckpt=ck, ckpt_k=K)
-                            wf.reverse(m, n, g_score=one, g_C=gC)
+                            wf.reverse(m, n, dtype=dtype, g_score=one, g_C=gC)
 
                         t_f = _time(fwd, reps)
                         t_s = _time(lambda: wf.select(C, ckpt=ck, ckpt_k=K), reps)
@@ -83,10 +83,11 @@ def main():
     p.add_argument("--sizes", default="256,1024,4096,16384")
     p.add_argument("--reps", type=int, default=10)
     p.add_argument("--rounds", type=int, default=3)
+    p.add_argument("--dtype", choices=("f32", "f64"), default="f32")
     args = p.parse_args()
     sizes = [int(x) for x in args.sizes.split(",")]
     print("m n | per tile G: forward, selection, selection + reverse [ms] | fastest tiles", flush=True)
-    sweep(sizes, args.reps, args.rounds)
+    sweep(sizes, args.reps, args.rounds, torch.float64 if args.dtype == "f64" else torch.float32)
 
 
 if __name__ == "__main__":

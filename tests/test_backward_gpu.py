@@ -72,7 +72,7 @@ def test_f32_adjoint_from_checkpoints(oracle_mod, shape):
         assert torch.equal(got, ref), f"ckpt_k={k}"
 
 
-@pytest.mark.parametrize("tile", [16, 64])
+@pytest.mark.parametrize("tile", [16, 32, 64])
 @pytest.mark.parametrize("shape", [(1, 1), (5, 300), (100, 70), (200, 333)])
 def test_f64_adjoint_bitwise(oracle_mod, shape, tile):
     m, n = shape

@@ -61,7 +61,7 @@ def test_f32_signed_inputs_bitwise(oracle_mod, shape):
     assert torch.equal(D, oracle_d(oracle_mod, C, "f32"))
 
 
-@pytest.mark.parametrize("tile", [16, 64])
+@pytest.mark.parametrize("tile", [16, 32, 64])
 @pytest.mark.parametrize("shape", [(1, 1), (5, 300), (100, 70), (200, 333)])
 def test_f64_bitwise(oracle_mod, shape, tile):
     m, n = shape

@@ -130,14 +130,19 @@ def test_paper_split_accuracies_are_reachable():
 
 def test_mi355x_table_accuracy():
     """Leave-one-out accuracy of the 1-NN rule on the MI355X tile table against the null
-    accuracy (the figures the design notes report)."""
+    accuracy, per column (the figures the design notes report)."""
     t = _table("mi355x_tile_table.txt")
+    assert t.shape == (16, 6)
     x = np.log2(t[:, :2])
-    fwd, rev = t[:, 2].astype(int), t[:, 3].astype(int)
-    assert knn.loo_accuracy(x, fwd) == pytest.approx(14 / 16)
-    assert knn.null_accuracy(fwd) == pytest.approx(11 / 16)
-    assert knn.loo_accuracy(x, rev) == pytest.approx(11 / 16)
-    assert knn.null_accuracy(rev) == pytest.approx(10 / 16)
+    expect = {2: (14, 11), 3: (11, 10), 4: (12, 8), 5: (12, 9)}  # column: (LOO hits, modal count)
+    for col, (hits, modal) in expect.items():
+        y = t[:, col].astype(int)
+        assert knn.loo_accuracy(x, y) == pytest.approx(hits / 16), col
+        assert knn.null_accuracy(y) == pytest.approx(modal / 16), col
+
+
+COLUMNS = ((_lib.WF_F32, 0, 2), (_lib.WF_F32, 1, 3), (_lib.WF_F64, 0, 4), (_lib.WF_F64, 1, 5),
+           (_lib.WF_I32, 0, 2))  # (dtype, reverse, table column); int32 reads the float32 forward column
 
 
 def test_library_predictor_equals_oracle_1nn():
@@ -153,17 +158,35 @@ def test_library_predictor_equals_oracle_1nn():
         d = np.sort(((x - q) ** 2).sum(axis=1))
         if len(d) > 1 and d[1] - d[0] < 1e-9 and d[0] > 0:
             continue  # equally near two shapes: rounding of log2 may decide either way
-        for col, rev in ((2, 0), (3, 1)):
+        for dtype, rev, col in COLUMNS:
             want = int(knn.predict(x, t[:, col].astype(int), [q])[0])
-            assert lib.wf_tile_predict(max(m, 1), max(n, 1), rev) == want, (m, n, rev)
+            assert lib.wf_tile_predict(dtype, max(m, 1), max(n, 1), rev) == want, (m, n, dtype, rev)
         checked += 1
     assert checked > 250
 
 
 def test_library_predictor_arguments():
     lib = _lib.load()
-    assert lib.wf_tile_predict(0, 5, 0) == _lib.WF_E_ARG
-    assert lib.wf_tile_predict(5, 0, 1) == _lib.WF_E_ARG
-    assert lib.wf_tile_predict(5, 5, 2) == _lib.WF_E_ARG
-    assert lib.wf_tile_predict(16384, 16384, 0) == 64
-    assert lib.wf_tile_predict(16384, 16384, 1) == 32
+    assert lib.wf_tile_predict(_lib.WF_F32, 0, 5, 0) == _lib.WF_E_ARG
+    assert lib.wf_tile_predict(_lib.WF_F32, 5, 0, 1) == _lib.WF_E_ARG
+    assert lib.wf_tile_predict(_lib.WF_F64, 5, 5, 2) == _lib.WF_E_ARG
+    assert lib.wf_tile_predict(7, 5, 5, 0) == _lib.WF_E_ARG
+    assert lib.wf_tile_predict(_lib.WF_I32, 5, 5, 1) == _lib.WF_E_UNSUPPORTED
+    assert lib.wf_tile_predict(_lib.WF_F32, 16384, 16384, 0) == 64
+    assert lib.wf_tile_predict(_lib.WF_F32, 16384, 16384, 1) == 32
+    assert lib.wf_tile_predict(_lib.WF_F64, 16384, 16384, 1) == 64
+
+
+def test_python_predict_tile():
+    import torch
+    import paper_2510_27351_amd as wf
+    assert wf.predict_tile(16384, 16384) == 64
+    assert wf.predict_tile(16384, 16384, reverse=True) == 32
+    assert wf.predict_tile(16384, 16384, reverse=True, dtype=torch.float64) == 64
+    assert wf.predict_tile(300, 200, dtype=torch.int32) == 64
+    with pytest.raises(wf.WfError):
+        wf.predict_tile(0, 5)
+    with pytest.raises(wf.WfError):
+        wf.predict_tile(5, 5, reverse=True, dtype=torch.int32)
+    with pytest.raises(wf.WfError):
+        wf.predict_tile(5, 5, dtype=torch.float16)
