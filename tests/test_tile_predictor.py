@@ -175,6 +175,12 @@ def test_library_predictor_arguments():
     assert lib.wf_tile_predict(_lib.WF_F32, 16384, 16384, 0) == 64
     assert lib.wf_tile_predict(_lib.WF_F32, 16384, 16384, 1) == 32
     assert lib.wf_tile_predict(_lib.WF_F64, 16384, 16384, 1) == 64
+    # extreme shapes still land on a row of the table
+    for m, n in ((1, 1), (1, 1 << 31), (1 << 40, 1), (1 << 40, 1 << 31)):
+        for dtype, rev, _ in COLUMNS:
+            assert lib.wf_tile_predict(dtype, m, n, rev) in (16, 32, 64), (m, n, dtype, rev)
+    assert lib.wf_tile_predict(_lib.WF_F32, 1, 1, 0) == 64  # nearest: 256 x 256
+    assert lib.wf_tile_predict(_lib.WF_F64, 1 << 40, 1, 1) == 16  # nearest: 16384 x 256
 
 
 def test_python_predict_tile():
