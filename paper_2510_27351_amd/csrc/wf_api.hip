@@ -123,9 +123,10 @@ const char* wf_error_string(int code) {
 }
 
 // The fastest tile G of the forward sweep (table, score, checkpoint grid K = 64) and of the
-// reverse sweep (timed behind the selection recompute, where it always runs) on MI355X for a
-// grid of shapes, in float32 and in float64 (python -m paper_2510_27351_amd.tile_sweep
-// [--dtype f64]: best of 3 rounds of 10 calls per tile).  The training set of the
+// reverse sweep (timed behind the selection recompute, where it always runs) on MI355X for
+// the 7 x 7 grid of shapes with m and n each a power of two from 256 to 16384, in float32 and
+// in float64 (python -m paper_2510_27351_amd.tile_sweep [--dtype f64]: best of 3 rounds of
+// 10 calls per tile).  The training set of the
 // nearest-neighbour rule below; the two element types get a column pair each, since the
 // float32 choices lose up to 18% when reused for float64.
 struct TileObs {
@@ -133,11 +134,18 @@ struct TileObs {
   int32_t fwd32, rev32, fwd64, rev64;
 };
 static const TileObs kTileTable[] = {
-    {256, 256, 64, 32, 32, 16},       {256, 1024, 64, 64, 64, 64},     {256, 4096, 64, 64, 64, 64},
-    {256, 16384, 64, 64, 64, 64},     {1024, 256, 32, 32, 32, 16},     {1024, 1024, 64, 32, 64, 64},
-    {1024, 4096, 64, 64, 64, 64},     {1024, 16384, 64, 64, 64, 64},   {4096, 256, 32, 32, 32, 16},
-    {4096, 1024, 32, 32, 32, 16},     {4096, 4096, 64, 32, 32, 64},    {4096, 16384, 64, 64, 64, 64},
-    {16384, 256, 32, 32, 32, 16},     {16384, 1024, 32, 32, 32, 16},   {16384, 4096, 64, 32, 32, 16},
+    {256, 256, 64, 32, 32, 16},    {256, 512, 64, 64, 64, 64},    {256, 1024, 64, 64, 64, 64},   {256, 2048, 64, 64, 64, 64},
+    {256, 4096, 64, 64, 64, 64},   {256, 8192, 64, 64, 64, 64},   {256, 16384, 64, 64, 64, 64},  {512, 256, 32, 32, 32, 16},
+    {512, 512, 64, 32, 32, 16},    {512, 1024, 64, 64, 64, 64},   {512, 2048, 64, 64, 64, 64},   {512, 4096, 64, 64, 64, 64},
+    {512, 8192, 64, 64, 64, 64},   {512, 16384, 64, 64, 64, 64},  {1024, 256, 32, 32, 32, 16},   {1024, 512, 64, 32, 32, 16},
+    {1024, 1024, 64, 32, 64, 16},  {1024, 2048, 64, 64, 64, 64},  {1024, 4096, 64, 64, 64, 64},  {1024, 8192, 64, 64, 64, 64},
+    {1024, 16384, 64, 64, 64, 64}, {2048, 256, 32, 32, 32, 16},   {2048, 512, 32, 32, 32, 16},   {2048, 1024, 64, 32, 32, 16},
+    {2048, 2048, 64, 32, 64, 64},  {2048, 4096, 64, 32, 64, 64},  {2048, 8192, 64, 64, 32, 64},  {2048, 16384, 64, 64, 64, 64},
+    {4096, 256, 32, 32, 32, 16},   {4096, 512, 32, 32, 32, 16},   {4096, 1024, 32, 32, 32, 16},  {4096, 2048, 64, 32, 32, 16},
+    {4096, 4096, 64, 32, 32, 64},  {4096, 8192, 64, 32, 64, 64},  {4096, 16384, 64, 64, 64, 64}, {8192, 256, 32, 32, 32, 16},
+    {8192, 512, 32, 32, 32, 16},   {8192, 1024, 32, 32, 32, 16},  {8192, 2048, 32, 32, 32, 16},  {8192, 4096, 64, 32, 32, 64},
+    {8192, 8192, 64, 32, 64, 64},  {8192, 16384, 64, 64, 64, 64}, {16384, 256, 32, 32, 32, 16},  {16384, 512, 32, 32, 32, 16},
+    {16384, 1024, 32, 32, 32, 16}, {16384, 2048, 32, 32, 32, 16}, {16384, 4096, 64, 32, 32, 16}, {16384, 8192, 64, 32, 64, 16},
     {16384, 16384, 64, 32, 64, 64},
 };
 

@@ -132,13 +132,27 @@ def test_mi355x_table_accuracy():
     """Leave-one-out accuracy of the 1-NN rule on the MI355X tile table against the null
     accuracy, per column (the figures the design notes report)."""
     t = _table("mi355x_tile_table.txt")
-    assert t.shape == (16, 6)
+    assert t.shape == (49, 6)
     x = np.log2(t[:, :2])
-    expect = {2: (14, 11), 3: (11, 10), 4: (12, 8), 5: (12, 9)}  # column: (LOO hits, modal count)
+    expect = {2: (45, 34), 3: (41, 30), 4: (41, 25), 5: (42, 26)}  # column: (LOO hits, modal count)
     for col, (hits, modal) in expect.items():
         y = t[:, col].astype(int)
-        assert knn.loo_accuracy(x, y) == pytest.approx(hits / 16), col
-        assert knn.null_accuracy(y) == pytest.approx(modal / 16), col
+        assert knn.loo_accuracy(x, y) == pytest.approx(hits / 49), col
+        assert knn.null_accuracy(y) == pytest.approx(modal / 49), col
+
+
+def test_mi355x_holdout():
+    """The rule's purpose, checked on shapes it did not see: fitted on the 4 x 4 sub-grid of
+    even powers of four (256, 1024, 4096, 16384), it is scored on the other 33 shapes of the
+    table."""
+    t = _table("mi355x_tile_table.txt")
+    x = np.log2(t[:, :2])
+    seen = np.isin(t[:, 0], [256, 1024, 4096, 16384]) & np.isin(t[:, 1], [256, 1024, 4096, 16384])
+    assert seen.sum() == 16
+    for col, hits in {2: 30, 3: 30, 4: 27, 5: 30}.items():
+        y = t[:, col].astype(int)
+        pred = knn.predict(x[seen], y[seen], x[~seen])
+        assert int(np.sum(pred == y[~seen])) == hits, col
 
 
 COLUMNS = ((_lib.WF_F32, 0, 2), (_lib.WF_F32, 1, 3), (_lib.WF_F64, 0, 4), (_lib.WF_F64, 1, 5),
