@@ -164,8 +164,8 @@ void wf_plan_destroy(wf_plan* plan);
 
 /*
  * Force the tile width (columns per handoff unit, 64 rows per band) used by later calls on
- * this process: 16, 32 or 64, or 0 to return to the automatic choice.  Returns WF_E_ARG for
- * any other value.  Used by the autotuner and the tests.
+ * this process: 16, 32 or 64, or 0 to return to the automatic choice (wf_tile_predict).
+ * Returns WF_E_ARG for any other value.  Used by the autotuner and the tests.
  */
 int wf_set_tile(int32_t tile);
 
