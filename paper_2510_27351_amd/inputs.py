@@ -63,3 +63,19 @@ def normal_clipped(m: int, n: int, seed: int, dtype=torch.float32) -> torch.Tens
 
 def integers(m: int, n: int, seed: int, lo: int = 0, hi: int = 1000) -> torch.Tensor:
     return torch.randint(lo, hi + 1, (m, n), dtype=torch.int32, generator=_gen(seed))
+
+
+def tridiagonal_dd(N: int, seed: int, margin: float = 1.0):
+    """A diagonally dominant tridiagonal system of size N as float64 diagonals (a, b, c) and
+    right-hand side d: off-diagonals uniform [-1, 1), |b[i]| = |a[i]| + |c[i]| + margin +
+    uniform [0, 1) with a random sign, d uniform [-1, 1); a[0] and c[N-1] (outside the
+    matrix) are 0."""
+    g = _gen(seed)
+    a = torch.rand(N, dtype=torch.float64, generator=g) * 2 - 1
+    c = torch.rand(N, dtype=torch.float64, generator=g) * 2 - 1
+    a[0] = 0.0
+    c[N - 1] = 0.0
+    sign = torch.where(torch.rand(N, dtype=torch.float64, generator=g) < 0.5, -1.0, 1.0)
+    b = sign * (a.abs() + c.abs() + margin + torch.rand(N, dtype=torch.float64, generator=g))
+    d = torch.rand(N, dtype=torch.float64, generator=g) * 2 - 1
+    return a, b, c, d
