@@ -82,3 +82,32 @@ def test_rejects_bad_input():
         tridiag.solve([0.0], [1.0, 2.0], [0.0], [1.0])
     with pytest.raises(ZeroDivisionError):
         tridiag.solve([0.0, 1.0], [0.0, 1.0], [1.0, 0.0], [1.0, 1.0])
+
+
+# Plausible mistakes planted in a private copy of the oracle's source; the dense-solve pin must
+# reject each one.  The shipped oracle is never modified.
+MUTATIONS = {
+    "back_substitution_sign": ("x[i] = dp[i] - cp[i] * x[i + 1]", "x[i] = dp[i] + cp[i] * x[i + 1]"),
+    "pivot_wrong_index": ("piv = b[i] - (a[i] * cp[i - 1] if i > 0 else 0.0)",
+                          "piv = b[i] - (a[i] * cp[i] if i > 0 else 0.0)"),
+    "pivot_dropped_term": ("piv = b[i] - (a[i] * cp[i - 1] if i > 0 else 0.0)", "piv = b[i]"),
+    "rhs_transposed_diagonal": ("dp[i] = (d[i] - (a[i] * dp[i - 1] if i > 0 else 0.0)) / piv",
+                                "dp[i] = (d[i] - (c[i] * dp[i - 1] if i > 0 else 0.0)) / piv"),
+    "super_diagonal_shift": ("cp[i] = c[i] / piv if i < N - 1 else 0.0",
+                             "cp[i] = c[i - 1] / piv if i < N - 1 else 0.0"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistakes(name):
+    import inspect
+    old, new = MUTATIONS[name]
+    src = inspect.getsource(tridiag.solve)
+    assert src.count(old) == 1, name
+    scope = {"np": np}
+    exec(src.replace(old, new), scope)
+    mutated = scope["solve"]
+    a, b, c, d = _system(50, seed=9)
+    x = mutated(a, b, c, d)
+    ref = np.linalg.solve(tridiag.dense(a, b, c), d)
+    assert np.max(np.abs(x - ref)) > 1e-6, name
