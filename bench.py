@@ -75,10 +75,26 @@ def measured_traffic(kernel: str):
     return float(val.group(1))
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and core counts (the oracle runs on one of them)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_available": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(C_cpu, budget_s: float = 15.0):
     """Times the CPU oracle (single-threaded C, float64, row by row) on a bounded leading
     block of the same matrix: forward with the selection map, then the adjoint of the score.
-    The block edge is grown from a probe so that the timed call takes about budget_s."""
+    The block edge is grown from a probe so that the timed call takes about budget_s (capped
+    at the whole matrix).  Returns the baseline entry and, when the block is the whole matrix,
+    the oracle's float64 table, selections and adjoint for the error report."""
     import numpy as np
 
     import oracle
@@ -88,17 +104,50 @@ def cpu_baseline(C_cpu, budget_s: float = 15.0):
     def run(r):
         block = C_cpu[:r, :r].numpy().astype(np.float64)
         t0 = time.perf_counter()
-        _, sel = oracle.forward(block, "f64", want_sel=True)
-        oracle.backward(sel, None, 1.0, "f64")
-        return time.perf_counter() - t0
+        D64, sel = oracle.forward(block, "f64", want_sel=True)
+        g64 = oracle.backward(sel, None, 1.0, "f64")
+        return time.perf_counter() - t0, (D64, sel, g64)
 
     r = min(n, 1024)
-    dt = run(r)
+    dt, _ = run(r)
     r2 = int(min(n, r * max(1.0, (budget_s / max(dt, 1e-3)) ** 0.5)))
-    dt = run(r2)
-    return {"value": r2 * r2 / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"top-left {r2}x{r2} block of the same matrix; f64 row-by-row C oracle, "
-                      f"forward with selection map then adjoint of the score, one thread, {dt:.2f} s"}
+    dt, outs = run(r2)
+    entry = {"value": r2 * r2 / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+             "sample": f"top-left {r2}x{r2} block of the same matrix; f64 row-by-row C oracle, "
+                       f"forward with selection map then adjoint of the score, one thread, {dt:.2f} s",
+             "host": host_cpu()}
+    return entry, (outs if r2 == n else None)
+
+
+def result_errors(C_cpu, D, score, gC, oracle64):
+    """Error of this run's results against the oracle: the table and score against the float64
+    forward (normwise, and elementwise with the worst cell: the inputs are signed, so D crosses
+    zero), the score's gradient against the float32 oracle (bitwise) and the float64 one
+    (cells that differ are float32/float64 selection flips at near-ties)."""
+    import numpy as np
+
+    import oracle
+    D64, sel64, g64 = oracle64
+    Dn = D.cpu().numpy()
+    diff = np.abs(Dn.astype(np.float64) - D64)
+    normwise = float(diff.max() / np.abs(D64).max())
+    rel = diff / np.maximum(np.abs(D64), np.finfo(np.float64).tiny)
+    w = np.unravel_index(int(np.argmax(rel)), rel.shape)
+    s64 = float(D64[-1, -1])
+    fwd = {"vs": "float64 oracle", "normwise_max_err": normwise, "elementwise_max_rel_err": float(rel[w]),
+           "worst_cell": [int(w[0]), int(w[1])], "score_rel_err": abs(float(score) - s64) / abs(s64)}
+    del diff, rel
+    D32, sel32 = oracle.forward(C_cpu.numpy(), "f32", want_sel=True)
+    fwd["bitwise_equal_f32_oracle"] = bool(np.array_equal(Dn, D32))
+    del Dn, D32
+    g = gC.cpu().numpy()
+    g32 = oracle.backward(sel32, None, 1.0, "f32")
+    g64s = oracle.backward(sel32, None, 1.0, "f64")
+    adj = {"bitwise_equal_f32_oracle": bool(np.array_equal(g, g32)),
+           "max_rel_err_vs_f64_adjoint_on_same_selections": float(np.abs(g - g64s).max()),
+           "cells_differing_from_f64_oracle": int(np.count_nonzero(g != g64)),
+           "selection_flips_f32_f64": int(np.count_nonzero(sel32 != sel64))}
+    return {"fwd": fwd, "adjoint": adj}
 
 
 def batch_rate(steps: int, warmup: int):
@@ -211,17 +260,21 @@ def main():
     Ks = (n + 63 + 63) // 64
     plane_bytes = nb * Ks * 64 * 32  # selection bit-planes: 32 bytes per band row and 64 slots
     top_bytes = (nb - 1) * n * es     # band top rows read back from the checkpoint grid
-    # algorithmic HBM bytes per launch: what each kernel must read and write at least
+    # Method bytes per launch: the inputs and outputs of the differentiable sweep each kernel
+    # must move at least.  The selection bit-planes that the recompute writes and the reverse
+    # sweep reads are an intermediate of this implementation, reported apart.
     kern = {
-        "fwd_kernel": (fwd_ms, 2 * cells * es + ck_bytes, "read C, write D and the checkpoint grid"),
-        "sel_kernel": (sel_ms, cells * es + top_bytes + plane_bytes,
-                       "read C and the band top rows, write the selection bit-planes"),
-        "adj_kernel": (rev_ms, plane_bytes + cells * es, "read the selection bit-planes, write g_C (g_D absent)"),
+        "fwd_kernel": (fwd_ms, 2 * cells * es + ck_bytes, 0, "read C, write D and the checkpoint grid"),
+        "sel_kernel": (sel_ms, cells * es + top_bytes, plane_bytes,
+                       "read C and the checkpoint grid's band rows (intermediate: writes the selection bit-planes)"),
+        "adj_kernel": (rev_ms, cells * es, plane_bytes,
+                       "write g_C, no g_D given (intermediate: reads the selection bit-planes)"),
     }
     eff = lambda nbytes, t_ms: nbytes / (t_ms * 1e-3) / 1e9  # noqa: E731
-    kernels = {k: {"ms": t, "bytes_per_launch": b, "achieved_GBps": eff(b, t),
-                   "frac": eff(b, t) / PEAK_HBM_GBPS, "bytes": what}
-               for k, (t, b, what) in kern.items()}
+    kernels = {k: {"ms": t, "bytes_per_launch": b, "intermediate_bytes_per_launch": ib,
+                   "achieved_GBps": eff(b, t), "frac": eff(b, t) / PEAK_HBM_GBPS,
+                   "measured_traffic_bytes": measured_traffic(k), "bytes": what}
+               for k, (t, b, ib, what) in kern.items()}
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     out = {
         "metric": "cells/sec and effective HBM GB/s (% peak), fwd and fwd+adjoint, n=16384",
@@ -260,8 +313,10 @@ def main():
         b["ratio_single_over_batch"] = (cells / (fwd_ms * 1e-3)) / b["cells_per_s"]
         out["batch"] = b
     if not args.no_cpu:
-        del D, gC
-        out["cpu_baseline"] = cpu_baseline(C_cpu)
+        base, oracle64 = cpu_baseline(C_cpu)
+        out["cpu_baseline"] = base
+        if oracle64 is not None:
+            out["errors"] = result_errors(C_cpu, D, wf_score.item(), gC, oracle64)
     print(json.dumps(out), flush=True)
 
 

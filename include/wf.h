@@ -163,6 +163,43 @@ int wf_batch_forward(wf_plan* plan, const void* C, void* D, void* scores, void* 
 void wf_plan_destroy(wf_plan* plan);
 
 /*
+ * Differentiable ragged batch: the forward with checkpoint grids, and the batched adjoint.
+ *
+ * wf_plan_ckpt_elems(plan, K)   elements of the buffer holding every instance's checkpoint
+ *                               grid for column spacing K (1..4096; 0 gives 0): instance i's
+ *                               grid (wf_ckpt_elems(m_i, n_i, K) elements, layout as for
+ *                               wf_forward) starts at element offset o_i, the grids packed in
+ *                               instance order with 256-byte aligned starts; -1 on bad input.
+ * wf_plan_ckpt_offsets(plan, K, offsets)  copies the o_i into a host array of 'batch'.
+ * wf_batch_forward_ckpt(plan, C, D, scores, ckpt, ckpt_k, stream)
+ *   wf_batch_forward that also writes every instance's checkpoint grid into 'ckpt'
+ *   (wf_plan_ckpt_elems(plan, ckpt_k) elements; NULL with ckpt_k = 0 for none).  The first
+ *   call with a new K rebuilds the plan's instance table (synchronizes the device); the
+ *   captured graph is keyed on (C, D, scores, ckpt) as for wf_batch_forward.
+ * wf_batch_backward(plan, C, ckpt, ckpt_k, D, g_scores, g_D, g_C, stream)
+ *   For every instance i, g_C_i = dL/dC_i for L = sum_i (sum(g_D_i * D_i) + g_scores[i] *
+ *   score_i), the routed adjoint of wf_backward, in two launches over all instances: the
+ *   selection recompute (every 64-row band of every instance at once) and one persistent
+ *   reverse sweep over a bottom-up (instance, band) work list.
+ *   C, D, g_D, g_C  device buffers in the plan's layout (wf_plan_elems elements; D and g_D may
+ *                   be NULL); the selections are recomputed from C and either the checkpoint
+ *                   grids of wf_batch_forward_ckpt (ckpt, ckpt_k > 0, D = NULL) or the saved
+ *                   tables (D, ckpt = NULL, ckpt_k = 0).
+ *   g_scores        'batch' elements, or NULL for 0.
+ *   WF_F32 and WF_F64 plans only (WF_E_UNSUPPORTED otherwise).  The first call allocates the
+ *   plan's selection bit-planes (4 bits per cell) and handoff words and synchronizes the
+ *   device; a call with another K than the previous one synchronizes it too.  Calls on one
+ *   plan must be ordered (the plan holds one set of selections).  Bitwise reproducible; each
+ *   instance's g_C equals wf_backward's on that instance.
+ */
+int64_t wf_plan_ckpt_elems(const wf_plan* plan, int32_t ckpt_k);
+int wf_plan_ckpt_offsets(const wf_plan* plan, int32_t ckpt_k, int64_t* offsets);
+int wf_batch_forward_ckpt(wf_plan* plan, const void* C, void* D, void* scores, void* ckpt, int32_t ckpt_k,
+                          void* stream);
+int wf_batch_backward(wf_plan* plan, const void* C, const void* ckpt, int32_t ckpt_k, const void* D,
+                      const void* g_scores, const void* g_D, void* g_C, void* stream);
+
+/*
  * Force the tile width (columns per handoff unit, 64 rows per band) used by later calls on
  * this process: 16, 32 or 64, or 0 to return to the automatic choice (wf_tile_predict).
  * Returns WF_E_ARG for any other value.  Used by the autotuner and the tests.
@@ -202,6 +239,21 @@ int64_t wf_trace_fetch(uint64_t* host, int64_t max_bands);
  * since the last check (the outputs of such a call are undefined).
  */
 int wf_last_async_error(void* stream);
+
+/*
+ * Fault injection, for tests of the failure path only.  Sets the mode of the current
+ * device's workspace for every later sweep on that device until it is set back to 0:
+ *   0  no fault (the default);
+ *   1  in wf_forward (and the ragged batch), band 0 publishes no boundary row: the band below
+ *      waits until its bounded wait (2 s) expires, raises WF_E_TIMEOUT and every workgroup of
+ *      the launch gives up and exits;
+ *   2  in the reverse sweep (wf_reverse / wf_backward), the bottom band publishes no routed
+ *      values, with the same effect.
+ * Outputs of a sweep that timed out are undefined; wf_last_async_error reports WF_E_TIMEOUT
+ * once, and later sweeps run normally.  Synchronizes the device.  Returns WF_E_ARG for any
+ * other mode.
+ */
+int wf_fault_inject(int32_t mode);
 
 /* Static, human-readable name of an error code. */
 const char* wf_error_string(int code);

@@ -146,42 +146,85 @@ def reverse(m: int, n: int, dtype: torch.dtype = torch.float32, g_score: torch.T
 class WfFunction(torch.autograd.Function):
     """Differentiable sweep: (D, score) = sweep(C), gradient by the adjoint sweep.
 
-    With table=False only the score is produced and the forward keeps the band rows of the
-    checkpoint grid (m/64 rows of n elements) instead of the table; with table=True the
-    table is saved and the backward recomputes the selections from it."""
+    C is one m x n instance or a batch (B, m, n) of equal-size instances (swept together by
+    one persistent launch per direction through a batch plan).  With table=False only the
+    score(s) are produced and the forward keeps the checkpoint grid (band rows every 64
+    rows, block columns every ckpt_k columns) instead of the table; with table=True the table
+    is saved and the backward recomputes the selections from it."""
 
     @staticmethod
-    def forward(ctx, C: torch.Tensor, table: bool):
+    def forward(ctx, C: torch.Tensor, table: bool, ckpt_k: int):
         C = C.contiguous()
-        m, n = C.shape
+        ctx.table = table
+        if C.dim() == 3:
+            plan = _batch_plan(C)
+            flat = C.view(-1)
+            if table:
+                scores, D, _ = plan.forward_ckpt(flat, 0, table=True)
+                ctx.save_for_backward(C, D)
+                ctx.plan = plan
+                return D.view(C.shape), scores
+            scores, _, ck = plan.forward_ckpt(flat, ckpt_k)
+            ctx.save_for_backward(C, ck)
+            ctx.plan, ctx.ckpt_k = plan, ckpt_k
+            return scores
         if table:
             D, score, _ = forward(C, table=True)
             ctx.save_for_backward(C, D)
-            ctx.mode = "table"
             return D, score
-        k = min(max(n, 1), 4096)
-        _, score, ckpt = forward(C, table=False, ckpt_k=k)
+        _, score, ckpt = forward(C, table=False, ckpt_k=ckpt_k)
         ctx.save_for_backward(C, ckpt)
-        ctx.mode = "ckpt"
-        ctx.ckpt_k = k
+        ctx.ckpt_k = ckpt_k
         return score
 
     @staticmethod
     def backward(ctx, *grads):
         C, saved = ctx.saved_tensors
-        if ctx.mode == "table":
+        if ctx.table:
             g_D, g_score = grads
             g_D = None if g_D is None else g_D.contiguous()
-            g_C = backward(C, g_score=g_score, g_D=g_D, D=saved)
         else:
             (g_score,) = grads
+            g_D = None
+        if C.dim() == 3:
+            plan = ctx.plan
+            gD = None if g_D is None else g_D.reshape(-1)
+            if ctx.table:
+                g_C = plan.backward(C.view(-1), g_scores=g_score, g_D=gD, D=saved.view(-1))
+            else:
+                g_C = plan.backward(C.view(-1), g_scores=g_score, ckpt=saved, ckpt_k=ctx.ckpt_k)
+            return g_C.view(C.shape), None, None
+        if ctx.table:
+            g_C = backward(C, g_score=g_score, g_D=g_D, D=saved)
+        else:
             g_C = backward(C, g_score=g_score, ckpt=saved, ckpt_k=ctx.ckpt_k)
-        return g_C, None
+        return g_C, None, None
 
 
-def sweep(C: torch.Tensor, table: bool = False):
-    """Autograd entry point: score (table=False) or (D, score) (table=True)."""
-    return WfFunction.apply(C, table)
+def sweep(C: torch.Tensor, table: bool = False, ckpt_k: int = 64):
+    """Autograd entry point: score (table=False) or (D, score) (table=True) of an m x n
+    instance, or scores of shape (B,) (and D of shape (B, m, n)) of a batch (B, m, n).
+    ckpt_k: column spacing of the checkpoint grid kept for the backward (table=False)."""
+    if C.dim() not in (2, 3):
+        raise ValueError("C must be (m, n) or (B, m, n)")
+    if not table and not 1 <= ckpt_k <= 4096:
+        raise ValueError("ckpt_k must be in [1, 4096]")
+    return WfFunction.apply(C, table, ckpt_k)
+
+
+_PLANS: dict = {}
+
+
+def _batch_plan(C: torch.Tensor) -> "Plan":
+    """The batch plan of B equal m x n instances stored contiguously (instance b at element
+    offset b*m*n), created once per (B, m, n, dtype, device) and kept."""
+    B, m, n = C.shape
+    key = (B, m, n, C.dtype, C.device)
+    plan = _PLANS.get(key)
+    if plan is None:
+        plan = Plan([m] * B, [n] * B, dtype=C.dtype, offsets=[b * m * n for b in range(B)], device=C.device)
+        _PLANS[key] = plan
+    return plan
 
 
 class Plan:
@@ -241,6 +284,73 @@ class Plan:
                                           scores.data_ptr(), _stream(self.device))
         _lib.check(rc, "wf_batch_forward")
         return scores, D
+
+    def ckpt_elems(self, ckpt_k: int) -> int:
+        k = _lib.load().wf_plan_ckpt_elems(self._h, ckpt_k)
+        if k < 0:
+            raise ValueError("invalid checkpoint spacing")
+        return k
+
+    def ckpt_offsets(self, ckpt_k: int):
+        out = (ctypes.c_int64 * self.batch)()
+        _lib.check(_lib.load().wf_plan_ckpt_offsets(self._h, ckpt_k, out), "wf_plan_ckpt_offsets")
+        return list(out)
+
+    def _check_buf(self, name, t, n=None):
+        n = self.elems if n is None else n
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or t.numel() < n:
+            raise ValueError(f"{name} must be a contiguous device buffer of the plan's dtype holding {n} elements")
+
+    def forward_ckpt(self, C: torch.Tensor, ckpt_k: int, table: bool = False, D: torch.Tensor | None = None,
+                     scores: torch.Tensor | None = None, ckpt: torch.Tensor | None = None):
+        """forward() that also writes every instance's checkpoint grid (ckpt_k > 0):
+        returns (scores, D, ckpt), the grids at ckpt_offsets(ckpt_k) of one buffer."""
+        self._check_buf("C", C)
+        if D is None and table:
+            D = torch.empty(self.elems, dtype=self.dtype, device=self.device)
+        if D is not None:
+            self._check_buf("D", D)
+        if scores is None:
+            scores = torch.empty(self.batch, dtype=self.dtype, device=self.device)
+        if ckpt is None and ckpt_k > 0:
+            ckpt = torch.empty(self.ckpt_elems(ckpt_k), dtype=self.dtype, device=self.device)
+        if ckpt is not None:
+            self._check_buf("ckpt", ckpt, self.ckpt_elems(ckpt_k))
+        rc = _lib.load().wf_batch_forward_ckpt(self._h, C.data_ptr(), D.data_ptr() if D is not None else None,
+                                               scores.data_ptr(), (ckpt.data_ptr() or None) if ckpt is not None
+                                               else None, ckpt_k, _stream(self.device))
+        _lib.check(rc, "wf_batch_forward_ckpt")
+        return scores, D, ckpt
+
+    def backward(self, C: torch.Tensor, g_scores: torch.Tensor | None = None, g_D: torch.Tensor | None = None,
+                 ckpt: torch.Tensor | None = None, ckpt_k: int = 0, D: torch.Tensor | None = None,
+                 g_C: torch.Tensor | None = None) -> torch.Tensor:
+        """Batched adjoint (wf_batch_backward): g_C in the plan's layout for
+        L = sum_i (sum(g_D_i * D_i) + g_scores[i] * score_i), the selections recomputed from C
+        and either the checkpoint grids (ckpt, ckpt_k) or the saved tables D."""
+        if (ckpt is None) == (D is None) or (ckpt is not None and ckpt_k < 1):
+            raise ValueError("pass exactly one of ckpt (with ckpt_k) or D")
+        self._check_buf("C", C)
+        for name, t in (("D", D), ("g_D", g_D), ("g_C", g_C)):
+            if t is not None:
+                self._check_buf(name, t)
+        if ckpt is not None:
+            self._check_buf("ckpt", ckpt, self.ckpt_elems(ckpt_k))
+        if g_scores is not None:
+            g_scores = g_scores.to(device=self.device, dtype=self.dtype).reshape(-1).contiguous()
+            if g_scores.numel() != self.batch:
+                raise ValueError("g_scores must hold one value per instance")
+        if g_C is None:
+            g_C = torch.empty(self.elems, dtype=self.dtype, device=self.device)
+        rc = _lib.load().wf_batch_backward(self._h, C.data_ptr(),
+                                           (ckpt.data_ptr() or None) if ckpt is not None else None,
+                                           ckpt_k if ckpt is not None else 0,
+                                           D.data_ptr() if D is not None else None,
+                                           g_scores.data_ptr() if g_scores is not None else None,
+                                           g_D.data_ptr() if g_D is not None else None, g_C.data_ptr(),
+                                           _stream(self.device))
+        _lib.check(rc, "wf_batch_backward")
+        return g_C
 
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:

@@ -49,6 +49,14 @@ def load():
     lib.wf_plan_config.restype = ctypes.c_int
     lib.wf_batch_forward.argtypes = [p, p, p, p, p]
     lib.wf_batch_forward.restype = ctypes.c_int
+    lib.wf_plan_ckpt_elems.argtypes = [p, i32]
+    lib.wf_plan_ckpt_elems.restype = i64
+    lib.wf_plan_ckpt_offsets.argtypes = [p, i32, pi64]
+    lib.wf_plan_ckpt_offsets.restype = ctypes.c_int
+    lib.wf_batch_forward_ckpt.argtypes = [p, p, p, p, p, i32, p]
+    lib.wf_batch_forward_ckpt.restype = ctypes.c_int
+    lib.wf_batch_backward.argtypes = [p, p, p, i32, p, p, p, p, p]
+    lib.wf_batch_backward.restype = ctypes.c_int
     lib.wf_plan_destroy.argtypes = [p]
     lib.wf_plan_destroy.restype = None
     lib.wf_ckpt_elems.argtypes = [i64, i64, i32]
@@ -65,6 +73,8 @@ def load():
     lib.wf_trace_enable.restype = ctypes.c_int
     lib.wf_trace_fetch.argtypes = [p, i64]
     lib.wf_trace_fetch.restype = i64
+    lib.wf_fault_inject.argtypes = [i32]
+    lib.wf_fault_inject.restype = ctypes.c_int
     lib.wf_version.argtypes = []
     lib.wf_version.restype = ctypes.c_int
     _lib = lib

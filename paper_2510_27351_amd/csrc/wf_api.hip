@@ -102,6 +102,9 @@ int choose_tile(int dtype, int64_t m, int64_t n, bool reverse) {
 int64_t nbands(int64_t m) { return (m + kBand - 1) / kBand; }
 
 }  // namespace
+
+int pick_tile(int dtype, int64_t m, int64_t n, bool reverse) { return choose_tile(dtype, m, n, reverse); }
+
 }  // namespace wf
 
 using namespace wf;
@@ -297,7 +300,6 @@ int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const
   sa.m = m;
   sa.n = n;
   sa.nb = (int32_t)nb;
-  sa.Q = (int32_t)(4 * Ks);
   sa.sel = ws->sel;
   sa.ctl = ws->ctl;
   if (launch_select(dtype, sa, grid, st) != hipSuccess) return WF_E_DEVICE;
@@ -328,7 +330,6 @@ int wf_reverse(int dtype, int64_t m, int64_t n, const void* g_score, const void*
     if (ws->sel_dtype != dtype || ws->sel_m != m || ws->sel_n != n) return WF_E_ARG;
   }
   const int64_t nb = nbands(m);
-  const int64_t Ks = (n + kBand - 1 + 63) / 64;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
   AdjArgs aa;
@@ -341,7 +342,6 @@ int wf_reverse(int dtype, int64_t m, int64_t n, const void* g_score, const void*
   aa.m = m;
   aa.n = n;
   aa.nb = (int32_t)nb;
-  aa.Q = (int32_t)(4 * Ks);
   aa.ctl = ws->ctl;
   aa.bnd = ws->bnd;
   aa.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
@@ -399,6 +399,20 @@ int64_t wf_trace_fetch(uint64_t* host, int64_t max_bands) {
   if (hipMemcpy(host, g_trace, (size_t)k * kTraceWords * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
     return -WF_E_DEVICE;
   return k;
+}
+
+int wf_fault_inject(int32_t mode) {
+  if (mode < 0 || mode > (int32_t)kFaultRevWithhold) return WF_E_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  DeviceWs* ws = nullptr;
+  int rc = ensure_ws(dev, 1, &ws);
+  if (rc != WF_OK) return rc;
+  // queued sweeps keep the mode they were launched under
+  if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+  const uint32_t v = (uint32_t)mode;
+  if (hipMemcpy(&ws->ctl->fault, &v, sizeof(v), hipMemcpyHostToDevice) != hipSuccess) return WF_E_DEVICE;
+  return WF_OK;
 }
 
 int wf_last_async_error(void* stream) {

@@ -41,8 +41,6 @@ __device__ __forceinline__ V opaque(V x) {
   return x;
 }
 
-enum : uint32_t { kSelNone = 0, kSelNW = 1, kSelN = 2, kSelW = 3 };
-
 // wave_shl:1 -- lane r receives lane r+1's value; lane 63 keeps 'old'.
 __device__ __forceinline__ uint32_t dpp_shl1_u32(uint32_t src, uint32_t old) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x130, 0xf, 0xf, false);
@@ -373,16 +371,31 @@ __device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const Sel
 }
 
 template <typename T>
+struct SelLds {
+  Vec4<T> S4[kBand * BCfg<T>::PITCH / 4];
+  Vec4<T> Tr4[BCfg<T>::RING / 4];
+};
+
+// One work item: band 'band' (piece 'piece' of it when the band is split) of the instance
+// 'a' describes.  The LDS counters must be zero on entry.
+template <typename T>
+__device__ __forceinline__ void sel_item(SelLds<T>& L, SelShared& sh, const SelArgs& a, int band, int piece) {
+  T* S = reinterpret_cast<T*>(L.S4);
+  T* Tr = reinterpret_cast<T*>(L.Tr4);
+  const int Ks = (int)((a.n + kBand - 1 + kSub - 1) / kSub);
+  const SelPiece pc = sel_piece(a, piece, Ks);
+  if (threadIdx.x < 64)
+    sel_compute<T>(S, Tr, sh, a, band, Ks, pc);
+  else
+    sel_loader<T>(S, Tr, sh, a, band, Ks, pc);
+}
+
+template <typename T>
 __global__ __launch_bounds__(128, 1) void sel_kernel(SelArgs a) {
-  using C = BCfg<T>;
-  __shared__ Vec4<T> S4[kBand * C::PITCH / 4];
-  __shared__ Vec4<T> Tr4[C::RING / 4];
+  __shared__ SelLds<T> L;
   __shared__ SelShared sh;
-  T* S = reinterpret_cast<T*>(S4);
-  T* Tr = reinterpret_cast<T*>(Tr4);
   Control* ctl = a.ctl;
   const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int Ks = (int)((a.n + kBand - 1 + kSub - 1) / kSub);
   if (threadIdx.x == 0) sh.abort = 0u;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -394,12 +407,51 @@ __global__ __launch_bounds__(128, 1) void sel_kernel(SelArgs a) {
     const int pieces = a.split > 0 ? 2 : 1;
     const int item = (int)sh.item;
     if (item >= a.nb * pieces || sh.abort != 0u) break;
-    const int band = item / pieces;
-    const SelPiece pc = sel_piece(a, item % pieces, Ks);
-    if (threadIdx.x < 64)
-      sel_compute<T>(S, Tr, sh, a, band, Ks, pc);
-    else
-      sel_loader<T>(S, Tr, sh, a, band, Ks, pc);
+    sel_item<T>(L, sh, a, item / pieces, item % pieces);
+    __syncthreads();
+  }
+  finish_launch(ctl, epoch);
+}
+
+// Batched selection recompute: one (instance, band) item at a time, bands whole.
+template <typename T>
+__global__ __launch_bounds__(128, 1) void sel_batch_kernel(BwdBatchArgs b) {
+  __shared__ SelLds<T> L;
+  __shared__ SelShared sh;
+  Control* ctl = b.ctl;
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) sh.abort = 0u;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      sh.loaded = 0u;
+      sh.steps = 0u;
+    }
+    claim_next(ctl, &sh.item, &sh.abort);
+    // the same for every lane: read it into a scalar register, so that the item's fields are
+    // scalar loads and kernel-wide values for the roles
+    const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.item);
+    if (item >= (uint32_t)b.n_items || sh.abort != 0u) break;
+    const BatchItem it = load_uniform(b.items + item);
+    const BwdInst in = load_uniform(b.inst + it.inst);
+    SelArgs a;
+    a.C = static_cast<const T*>(b.C) + in.off;
+    if (b.ckpt_k > 0) {  // band rows of the instance's checkpoint grid
+      a.top = static_cast<const T*>(b.top) + in.ck_off;
+      a.ld_top = in.n;
+    } else {  // rows 64b+63 of the instance's saved table
+      a.top = static_cast<const T*>(b.top) + in.off + 63 * in.n;
+      a.ld_top = 64 * in.n;
+    }
+    a.ldc = in.n;
+    a.m = in.m;
+    a.n = in.n;
+    a.nb = in.nb;
+    a.sel = b.sel + in.sel_off;
+    a.ctl = ctl;
+    a.split = 0;
+    a.left = nullptr;
+    a.ld_left = 0;
+    sel_item<T>(L, sh, a, it.band, 0);
     __syncthreads();
   }
   finish_launch(ctl, epoch);
@@ -1022,6 +1074,9 @@ __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, Ad
   const int lane = threadIdx.x & 63;
   const int64_t n = opaque(a.n);
   const int S0 = kSub * Ks, Us = S0 / G;
+  // an injected fault (tests of the failure path) makes the bottom band withhold its values
+  const bool withhold = band == a.nb - 1 && __hip_atomic_load(&a.ctl->fault, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT) == kFaultRevWithhold;
   uint64_t waited = 0;
   for (int u = 0; u < Us;) {
     uint32_t done;
@@ -1038,7 +1093,7 @@ __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, Ad
     if (mark) tr[17] = __builtin_amdgcn_s_memrealtime();
     // lane 0 of the compute wave handled slots [S0 - G(u+k), S0 - Gu) = columns
     const int s = S0 - G * (u + k) + lane;
-    if (band > 0 && lane < cols && s < n) {
+    if (band > 0 && !withhold && lane < cols && s < n) {
       const T A = S[s & C::MASK];  // row 0
       const uint32_t* pr = PubR + 4 * ((s >> 6) & (C::NSUB - 1));
       const int h = (s >> 5) & 1, bit = s & 31;
@@ -1058,21 +1113,45 @@ __device__ __forceinline__ void adj_publish(const T* S, const uint32_t* PubR, Ad
   if (tr && lane == 0) tr[18] = waited;
 }
 
+template <typename T>
+struct AdjLds {
+  Vec4<T> S4[kBand * BCfg<T>::PITCH / 4];
+  uint32_t F[kBand * BCfg<T>::FPITCH];
+  uint32_t PubR[4 * BCfg<T>::NSUB];
+};
+
+// One band of the instance 'a' describes, all six roles.  The LDS counters must be zero on
+// entry.
+template <typename T, int G>
+__device__ __forceinline__ void adj_band(AdjLds<T>& L, AdjShared& sh, const AdjArgs& a, int band, uint32_t epoch,
+                                         uint64_t* tr) {
+  T* S = reinterpret_cast<T*>(L.S4);
+  const int wave = threadIdx.x >> 6;
+  const int Ks = (int)((a.n + kBand - 1 + kSub - 1) / kSub);
+  if (wave == 0)
+    adj_compute<T, G>(S, L.F, sh, a.ctl, Ks, tr);
+  else if (wave == 1)
+    a.gD ? adj_loader<T, G, true, 0>(S, L.F, L.PubR, sh, a, band, Ks, tr)
+         : adj_loader<T, G, false, 0>(S, L.F, L.PubR, sh, a, band, Ks, tr);
+  else if (wave == 2)
+    adj_poll<T, G>(S, sh, a, band, Ks, epoch, tr);
+  else if (wave == 3)
+    adj_store<T, G>(S, sh, a, band, Ks, tr);
+  else if (wave == 4)
+    adj_publish<T, G>(S, L.PubR, sh, a, band, Ks, epoch, tr);
+  else
+    adj_loader<T, G, false, 1>(S, L.F, L.PubR, sh, a, band, Ks, tr);
+}
+
 // TRACE = false compiles every trace statement out (the production instance); the traced
 // instance is launched only while tracing is enabled.
 template <typename T, int G, bool TRACE>
 __global__ __launch_bounds__(kAdjThreads, 1) void adj_kernel(AdjArgs a) {
-  using C = BCfg<T>;
   if constexpr (!TRACE) a.trace = nullptr;
-  __shared__ Vec4<T> S4[kBand * C::PITCH / 4];
-  __shared__ uint32_t F[kBand * C::FPITCH];
-  __shared__ uint32_t PubR[4 * C::NSUB];
+  __shared__ AdjLds<T> L;
   __shared__ AdjShared sh;
-  T* S = reinterpret_cast<T*>(S4);
-  const int wave = threadIdx.x >> 6;
   Control* ctl = a.ctl;
   const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int Ks = (int)((a.n + kBand - 1 + kSub - 1) / kSub);
   if (threadIdx.x == 0) sh.abort = 0u;
   for (;;) {
     if (threadIdx.x < kAdjCounters) sh.ctr[threadIdx.x] = 0u;
@@ -1081,20 +1160,46 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adj_kernel(AdjArgs a) {
     const int band = a.nb - 1 - (int)sh.item;  // bottom band first
     uint64_t* tr = a.trace ? a.trace + (int64_t)band * kTraceWords : nullptr;
     if (tr && threadIdx.x == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
-    if (wave == 0)
-      adj_compute<T, G>(S, F, sh, ctl, Ks, tr);
-    else if (wave == 1)
-      a.gD ? adj_loader<T, G, true, 0>(S, F, PubR, sh, a, band, Ks, tr)
-           : adj_loader<T, G, false, 0>(S, F, PubR, sh, a, band, Ks, tr);
-    else if (wave == 2)
-      adj_poll<T, G>(S, sh, a, band, Ks, epoch, tr);
-    else if (wave == 3)
-      adj_store<T, G>(S, sh, a, band, Ks, tr);
-    else if (wave == 4)
-      adj_publish<T, G>(S, PubR, sh, a, band, Ks, epoch, tr);
-    else
-      adj_loader<T, G, false, 1>(S, F, PubR, sh, a, band, Ks, tr);
+    adj_band<T, G>(L, sh, a, band, epoch, tr);
     if (tr && threadIdx.x == 3 * 64) tr[3] = __builtin_amdgcn_s_memrealtime();
+    __syncthreads();
+  }
+  finish_launch(ctl, epoch);
+}
+
+// Batched reverse sweep: (instance, band) items claimed in list order, which puts every
+// band after the band below it of the same instance, so a claimed band only ever waits for
+// bands that were claimed before it and are running or done.
+template <typename T, int G>
+__global__ __launch_bounds__(kAdjThreads, 1) void adj_batch_kernel(BwdBatchArgs b) {
+  __shared__ AdjLds<T> L;
+  __shared__ AdjShared sh;
+  Control* ctl = b.ctl;
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) sh.abort = 0u;
+  for (;;) {
+    if (threadIdx.x < kAdjCounters) sh.ctr[threadIdx.x] = 0u;
+    claim_next(ctl, &sh.item, &sh.abort);
+    // the same for every lane: read it into a scalar register, so that the item's fields are
+    // scalar loads and kernel-wide values for the roles
+    const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.item);
+    if (item >= (uint32_t)b.n_items || sh.abort != 0u) break;
+    const BatchItem it = load_uniform(b.items + item);
+    const BwdInst in = load_uniform(b.inst + it.inst);
+    AdjArgs a;
+    a.sel = b.sel + in.sel_off;
+    a.gD = b.gD ? static_cast<const T*>(b.gD) + in.off : nullptr;
+    a.gscore = b.gscores ? static_cast<const T*>(b.gscores) + it.inst : nullptr;
+    a.gC = static_cast<T*>(b.gC) + in.off;
+    a.ldgd = in.n;
+    a.ldgc = in.n;
+    a.m = in.m;
+    a.n = in.n;
+    a.nb = in.nb;
+    a.ctl = ctl;
+    a.bnd = b.bnd + in.bnd_off;
+    a.trace = nullptr;
+    adj_band<T, G>(L, sh, a, it.band, epoch, nullptr);
     __syncthreads();
   }
   finish_launch(ctl, epoch);
@@ -1131,6 +1236,34 @@ hipError_t launch_adjoint(int dtype, int tile, const AdjArgs& a, int grid, hipSt
   switch (dtype) {
     case 0: return launch_adj_t<float>(tile, a, grid, s);
     case 1: return launch_adj_t<double>(tile, a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_select_batch(int dtype, const BwdBatchArgs& b, int grid, hipStream_t s) {
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL((sel_batch_kernel<float>), dim3(grid), dim3(128), 0, s, b); break;
+    case 1: hipLaunchKernelGGL((sel_batch_kernel<double>), dim3(grid), dim3(128), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_batch_t(int tile, const BwdBatchArgs& b, int grid, hipStream_t s) {
+  switch (tile) {
+    case 16: hipLaunchKernelGGL((adj_batch_kernel<T, 16>), dim3(grid), dim3(kAdjThreads), 0, s, b); break;
+    case 32: hipLaunchKernelGGL((adj_batch_kernel<T, 32>), dim3(grid), dim3(kAdjThreads), 0, s, b); break;
+    case 64: hipLaunchKernelGGL((adj_batch_kernel<T, 64>), dim3(grid), dim3(kAdjThreads), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_batch(int dtype, int tile, const BwdBatchArgs& b, int grid, hipStream_t s) {
+  switch (dtype) {
+    case 0: return launch_adj_batch_t<float>(tile, b, grid, s);
+    case 1: return launch_adj_batch_t<double>(tile, b, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

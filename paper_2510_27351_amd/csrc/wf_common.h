@@ -278,6 +278,23 @@ __device__ __forceinline__ uint64_t load_word(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Loads a small struct that is the same for every lane and moves it word by word into scalar
+// registers, so that its fields are wave-uniform values to the compiler (a work item's
+// description, read from a table the kernel also writes near, would otherwise stay in vector
+// registers).
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "word-sized struct expected");
+  constexpr int NW = (int)(sizeof(S) / 4);
+  S v = *p;
+  uint32_t w[NW];
+  __builtin_memcpy(w, &v, sizeof(S));
+#pragma unroll
+  for (int i = 0; i < NW; ++i) w[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)w[i]);
+  __builtin_memcpy(&v, w, sizeof(S));
+  return v;
+}
+
 // Claims the next work index for the whole workgroup (thread 0 claims, LDS broadcasts).
 // Also snapshots the abort flag so that the loop exit is uniform across the workgroup.
 __device__ __forceinline__ void claim_next(Control* ctl, uint32_t* sh_item, uint32_t* sh_abort) {

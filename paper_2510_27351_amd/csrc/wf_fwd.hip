@@ -646,6 +646,9 @@ __device__ __forceinline__ void publish_band(const T* S, Shared& sh, const FwdAr
   const int nb64 = (int)((m + kBand - 1) / kBand);  // 64-row bands of the checkpoint grid
   const bool last_band = band == a.nb - 1;
   T* ck_rows = static_cast<T*>(a.ckpt);
+  // an injected fault (tests of the failure path) makes band 0 withhold its boundary row
+  const bool withhold =
+      band == 0 && __hip_atomic_load(&a.ctl->fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == kFaultFwdWithhold;
   uint64_t waited = 0;
   for (int u = 0; u < Us;) {
     uint32_t done;
@@ -664,7 +667,7 @@ __device__ __forceinline__ void publish_band(const T* S, Shared& sh, const FwdAr
       const int slot = (G * u + lane) & C::MASK;
       // the band's last row, row H-1, finished column Gu + lane - skew(H-1) at this step
       const int64_t j = (int64_t)G * u + lane - C::skew(C::H - 1);
-      if (!last_band && j >= 0 && j < n) {
+      if (!last_band && !withhold && j >= 0 && j < n) {
         const T x = S[(C::H - 1) * C::PITCH + slot];
 #pragma unroll
         for (int q = 0; q < W; ++q) store_word(a.bnd + ((int64_t)band * n + j) * W + q, tagged(E::word(x, q), epoch));
@@ -774,12 +777,12 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_batch_kernel(BatchArgs b) {
     a.C = static_cast<const T*>(b.C) + in.off;
     a.D = b.D ? static_cast<T*>(b.D) + in.off : nullptr;
     a.score = static_cast<T*>(b.scores) + it.inst;
-    a.ckpt = nullptr;
+    a.ckpt = b.ckpt ? static_cast<T*>(b.ckpt) + in.ck_off : nullptr;
     a.ldc = in.n;
     a.ldd = in.n;
     a.m = in.m;
     a.n = in.n;
-    a.ckpt_k = 0;
+    a.ckpt_k = b.ckpt ? b.ckpt_k : 0;
     a.nb = in.nb;
     a.ctl = ctl;
     a.bnd = b.bnd + in.bnd_off;

@@ -23,9 +23,14 @@ struct Control {
   uint32_t epoch;   // tag carried by this launch's handoff words (never 0)
   uint32_t abort;   // set when a bounded wait expires; makes every wait give up
   uint32_t err;     // sticky error bits (kErrTimeout); read and cleared by the host
-  uint32_t pad[11];
+  uint32_t fault;   // injected fault for tests of the failure path (kFault*), 0 = none
+  uint32_t pad[10];
 };
 constexpr uint32_t kErrTimeout = 1u;
+// Injected faults (wf_fault_inject): a band withholds the boundary values another band
+// waits for, so that the waiting band's bounded wait expires and the launch aborts.
+constexpr uint32_t kFaultFwdWithhold = 1u;  // forward: band 0 publishes no boundary row
+constexpr uint32_t kFaultRevWithhold = 2u;  // reverse: the bottom band publishes no routed values
 
 // Arguments of the single-instance forward sweep.
 struct FwdArgs {
@@ -59,16 +64,16 @@ constexpr int kTraceWords = 24;
 
 // Arguments of the selection recompute (first half of the adjoint): every 64-row band is
 // swept again from its top row -- a checkpoint row, or a row of the saved table -- and
-// emits the 2-bit predecessor code of each cell (0 none / outside, 1 NW, 2 N, 3 W), packed
-// 16 per 32-bit word: word q of lane r of band b holds slots 16q .. 16q+15 of row 64b + r
-// (slot = row-in-band + column), at sel[(b * Q + q) * 64 + r], Q = ceil((n + 63) / 16).
+// emits three bit-planes per band row (W selected, N selected, NW selected; one bit per
+// cell).  For band b, 64-slot sub-chunk k (slot = row-in-band + column) and lane r, eight
+// 32-bit words at sel[((b * Ks + k) * 64 + r) * 8]: W[0..1], N[0..1], NW[0..1], 0, 0, bit j
+// of word h of a plane being slot 64k + 32h + j of row 64b + r; Ks = ceil((n + 63) / 64).
 struct SelArgs {
   const void* C;
   const void* top;    // row 64b-1 of band b >= 1 is at top + (b-1) * ld_top
   int64_t ldc, ld_top;
   int64_t m, n;
   int32_t nb;         // 64-row bands
-  int32_t Q;          // sel words per lane per band
   uint32_t* sel;
   Control* ctl;
   // Column split (split > 0): each band is swept as two pieces, columns [0, split) and
@@ -80,7 +85,7 @@ struct SelArgs {
 };
 
 // Arguments of the reverse adjoint sweep (second half): bands of 64 rows from the bottom
-// up, each from right to left, reading the selection codes and the upstream gradient.
+// up, each from right to left, reading the selection bit-planes and the upstream gradient.
 struct AdjArgs {
   const uint32_t* sel;
   const void* gD;       // may be null (zero)
@@ -89,7 +94,6 @@ struct AdjArgs {
   int64_t ldgd, ldgc;
   int64_t m, n;
   int32_t nb;           // 64-row bands
-  int32_t Q;
   Control* ctl;
   uint64_t* bnd;        // (nb-1) * n * 2 * words-per-element handoff words
   uint64_t* trace;
@@ -102,6 +106,7 @@ struct BatchInst {
   int64_t off;
   int64_t m, n;
   int64_t bnd_off;
+  int64_t ck_off;   // element offset of the instance's checkpoint grid (when one is written)
   int32_t nb;       // bands of the instance
   int32_t pad;
 };
@@ -113,12 +118,46 @@ struct BatchArgs {
   const void* C;
   void* D;              // may be null (scores only)
   void* scores;         // one element per instance
+  void* ckpt;           // may be null: every instance's checkpoint grid, at its ck_off
+  int32_t ckpt_k;       // 0 = no checkpoints
+  int32_t pad2;
   const BatchInst* inst;
   const BatchItem* items;
   int32_t n_items;
   int32_t pad;
   Control* ctl;
   uint64_t* bnd;
+};
+
+// Batched adjoint: instance i's C, D, gD and gC at element offset 'off' (leading dimension
+// n), its checkpoint grid at ck_off, its selection bit-planes at word sel_off of the plan's
+// selection buffer and its reverse handoff words at word bnd_off.
+struct BwdInst {
+  int64_t off;
+  int64_t m, n;
+  int64_t ck_off;
+  int64_t sel_off;
+  int64_t bnd_off;
+  int32_t nb;       // 64-row bands
+  int32_t pad;
+};
+// Work items of the batched adjoint are (instance, band) pairs (BatchItem), ordered from the
+// bottom band up: every instance's last band, then every second-to-last band, and so on, so
+// that in the reverse sweep a band always follows the band below it.  The selection
+// recompute, whose bands are independent, takes the same list.
+struct BwdBatchArgs {
+  const void* C;
+  const void* top;      // the checkpoint grids (ckpt_k > 0) or the saved tables (ckpt_k = 0)
+  int32_t ckpt_k;
+  int32_t n_items;
+  const void* gD;       // may be null (zero)
+  const void* gscores;  // one element per instance, or null (zero)
+  void* gC;
+  const BwdInst* inst;
+  const BatchItem* items;
+  uint32_t* sel;
+  uint64_t* bnd;
+  Control* ctl;
 };
 
 // Host-side launchers (defined in wf_fwd.hip).  'tile' is 16, 32 or 64.
@@ -130,6 +169,8 @@ hipError_t launch_forward_batch(int dtype, int tile, int rows, const BatchArgs& 
 // Adjoint launchers (defined in wf_bwd.hip), float (dtype 0) and double (dtype 1) only.
 hipError_t launch_select(int dtype, const SelArgs& a, int grid, hipStream_t s);
 hipError_t launch_adjoint(int dtype, int tile, const AdjArgs& a, int grid, hipStream_t s);
+hipError_t launch_select_batch(int dtype, const BwdBatchArgs& b, int grid, hipStream_t s);
+hipError_t launch_adjoint_batch(int dtype, int tile, const BwdBatchArgs& b, int grid, hipStream_t s);
 
 // ---------------------------------------------------------------------------------------
 // Host runtime (defined in wf_api.hip).
@@ -148,6 +189,9 @@ struct DeviceWs {
 // Returns the workspace of device 'dev' with at least 'words' handoff words.
 int ensure_ws(int dev, size_t words, DeviceWs** out);
 int elem_size(int dtype);       // bytes per element, 0 for an invalid dtype
+// Tile of the single-instance sweeps for a shape: the override (wf_set_tile, then WF_TILE),
+// else the nearest-neighbour prediction (wf_tile_predict).  dtype, m and n must be valid.
+int pick_tile(int dtype, int64_t m, int64_t n, bool reverse);
 int words_per_elem(int dtype);  // 32-bit payload words per element in the handoff words
 
 // Largest leading dimension, in bytes: a band of up to 128 rows is addressed with 32-bit

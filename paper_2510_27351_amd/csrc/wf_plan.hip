@@ -30,15 +30,38 @@ struct wf_plan {
   BatchInst* inst = nullptr;      // device copy of the instance table for 'rows'
   BatchItem* items = nullptr;     // device work list for 'rows'
   int32_t n_items = 0;
+  int32_t ck_k = 0;               // checkpoint spacing K the instance table's ck_off is for
   uint64_t* bnd = nullptr;        // handoff words (sized for one row per band, the larger)
   hipStream_t cap = nullptr;      // private stream used only to capture the graph
   hipGraphExec_t exec = nullptr;  // captured launch, valid for the pointers below
   const void* g_C = nullptr;
   void* g_D = nullptr;
   void* g_scores = nullptr;
+  void* g_ckpt = nullptr;
+  // batched adjoint, set up by the first wf_batch_backward
+  BwdInst* b_inst = nullptr;      // instance table (checkpoint offsets for b_k)
+  BatchItem* b_items = nullptr;   // bottom-up work list
+  int32_t b_n_items = 0;
+  int32_t b_k = -1;               // K of b_inst's checkpoint offsets (-1: not built)
+  uint32_t* b_sel = nullptr;      // selection bit-planes of every instance
+  uint64_t* b_bnd = nullptr;      // reverse handoff words of every instance
 };
 
 namespace {
+
+// Element offsets of every instance's checkpoint grid for spacing K, packed in instance order
+// with 256-byte aligned starts; returns the total number of elements.
+int64_t ckpt_layout(const wf_plan& p, int32_t K, std::vector<int64_t>* offs) {
+  const int64_t align = 256 / elem_size(p.dtype);
+  int64_t at = 0;
+  if (offs) offs->resize(p.batch);
+  for (int32_t i = 0; i < p.batch; ++i) {
+    if (offs) (*offs)[i] = at;
+    const int64_t e = K > 0 ? wf_ckpt_elems(p.m[i], p.n[i], K) : 0;
+    at += (e + align - 1) / align * align;
+  }
+  return at;
+}
 
 // Work list for bands of 64*rows rows.  Items are ordered band index first: every band-0
 // item of every instance, then every band-1 item, and so on; within one band index,
@@ -46,10 +69,12 @@ namespace {
 // above it of the same instance (the persistent workgroups can never wait on an unclaimed
 // item), and by the time it is claimed the band above has usually been running for a
 // whole round of the grid, so little time is lost to pipeline fill.
-void build_work(const wf_plan& p, int rows, std::vector<BatchInst>& inst, std::vector<BatchItem>& items,
-                size_t& bnd_words) {
+void build_work(const wf_plan& p, int rows, int32_t K, std::vector<BatchInst>& inst,
+                std::vector<BatchItem>& items, size_t& bnd_words) {
   const int64_t H = (int64_t)kBand * rows;
   const int W = words_per_elem(p.dtype);
+  std::vector<int64_t> ck;
+  ckpt_layout(p, K, &ck);
   inst.resize(p.batch);
   bnd_words = 0;
   int32_t max_nb = 0;
@@ -60,6 +85,7 @@ void build_work(const wf_plan& p, int rows, std::vector<BatchInst>& inst, std::v
     b.n = p.n[i];
     b.nb = (int32_t)((p.m[i] + H - 1) / H);
     b.pad = 0;
+    b.ck_off = ck[i];
     b.bnd_off = (int64_t)bnd_words;
     bnd_words += (size_t)(b.nb - 1) * (size_t)p.n[i] * W;
     max_nb = std::max(max_nb, b.nb);
@@ -77,11 +103,11 @@ void build_work(const wf_plan& p, int rows, std::vector<BatchInst>& inst, std::v
   if (bnd_words == 0) bnd_words = 1;
 }
 
-int upload_work(wf_plan& p, int rows) {
+int upload_work(wf_plan& p, int rows, int32_t K) {
   std::vector<BatchInst> inst;
   std::vector<BatchItem> items;
   size_t words = 0;
-  build_work(p, rows, inst, items, words);
+  build_work(p, rows, K, inst, items, words);
   if (p.inst) (void)hipFree(p.inst);
   if (p.items) (void)hipFree(p.items);
   p.inst = nullptr;
@@ -93,14 +119,18 @@ int upload_work(wf_plan& p, int rows) {
     return WF_E_DEVICE;
   p.n_items = (int32_t)items.size();
   p.rows = rows;
+  p.ck_k = K;
   return WF_OK;
 }
 
-hipError_t launch_plan(const wf_plan& p, const void* C, void* D, void* scores, hipStream_t s) {
+hipError_t launch_plan(const wf_plan& p, const void* C, void* D, void* scores, void* ckpt, hipStream_t s) {
   BatchArgs b;
   b.C = C;
   b.D = D;
   b.scores = scores;
+  b.ckpt = ckpt;
+  b.ckpt_k = ckpt ? p.ck_k : 0;
+  b.pad2 = 0;
   b.inst = p.inst;
   b.items = p.items;
   b.n_items = p.n_items;
@@ -193,13 +223,13 @@ int autotune(wf_plan& p, int want_tile, int want_rows, hipStream_t s) {
   for (int rows : {1, 2}) {
     if (want_rows && rows != want_rows) continue;
     if (rows == 2 && p.dtype == WF_F64) continue;
-    if ((rc = upload_work(p, rows)) != WF_OK) goto done;
+    if ((rc = upload_work(p, rows, 0)) != WF_OK) goto done;
     for (int tile : {16, 32, 64}) {
       if (want_tile && tile != want_tile) continue;
       p.tile = tile;
       float t_min = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
-        if (hipEventRecord(e0, s) != hipSuccess || launch_plan(p, C, D, sc, s) != hipSuccess ||
+        if (hipEventRecord(e0, s) != hipSuccess || launch_plan(p, C, D, sc, nullptr, s) != hipSuccess ||
             hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
           rc = WF_E_DEVICE;
           goto done;
@@ -238,7 +268,85 @@ void free_plan(wf_plan* p) {
   if (p->inst) (void)hipFree(p->inst);
   if (p->items) (void)hipFree(p->items);
   if (p->bnd) (void)hipFree(p->bnd);
+  if (p->b_inst) (void)hipFree(p->b_inst);
+  if (p->b_items) (void)hipFree(p->b_items);
+  if (p->b_sel) (void)hipFree(p->b_sel);
+  if (p->b_bnd) (void)hipFree(p->b_bnd);
   delete p;
+}
+
+// Sets up (or, for another K, rebuilds) the batched adjoint's tables and buffers: instance
+// table, bottom-up work list, selection bit-planes and reverse handoff words.  Allocates and
+// synchronizes the device the first time.
+int ensure_bwd(wf_plan& p, int32_t K) {
+  if (p.b_k == K) return WF_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+  std::vector<int64_t> ck;
+  ckpt_layout(p, K, &ck);
+  const int W = words_per_elem(p.dtype);
+  std::vector<BwdInst> inst(p.batch);
+  int64_t sel_words = 0, bnd_words = 0;
+  int32_t max_nb = 0;
+  for (int32_t i = 0; i < p.batch; ++i) {
+    BwdInst& b = inst[i];
+    b.off = p.off[i];
+    b.m = p.m[i];
+    b.n = p.n[i];
+    b.ck_off = ck[i];
+    b.nb = (int32_t)((p.m[i] + kBand - 1) / kBand);
+    b.pad = 0;
+    b.sel_off = sel_words;
+    b.bnd_off = bnd_words;
+    const int64_t Ks = (p.n[i] + kBand - 1 + 63) / 64;
+    sel_words += (int64_t)b.nb * Ks * 64 * 8;
+    bnd_words += (int64_t)(b.nb - 1) * p.n[i] * 2 * W;
+    max_nb = std::max(max_nb, b.nb);
+  }
+  // bottom-up, band-major: the last band of every instance, then the one above it, ...;
+  // within one step instances with more bands first
+  std::vector<int32_t> order(p.batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    if (inst[x].nb != inst[y].nb) return inst[x].nb > inst[y].nb;
+    return inst[x].n > inst[y].n;
+  });
+  std::vector<BatchItem> items;
+  for (int32_t t = 0; t < max_nb; ++t)
+    for (int32_t i : order)
+      if (t < inst[i].nb) items.push_back(BatchItem{i, inst[i].nb - 1 - t});
+  if (items.size() >= (size_t)INT32_MAX) return WF_E_ARG;
+  const bool first = p.b_k < 0;
+  if (p.b_inst) (void)hipFree(p.b_inst);
+  p.b_inst = nullptr;
+  if (hipMalloc(&p.b_inst, inst.size() * sizeof(BwdInst)) != hipSuccess) { p.b_inst = nullptr; return WF_E_NOMEM; }
+  if (hipMemcpy(p.b_inst, inst.data(), inst.size() * sizeof(BwdInst), hipMemcpyHostToDevice) != hipSuccess)
+    return WF_E_DEVICE;
+  if (first) {
+    if (hipMalloc(&p.b_items, items.size() * sizeof(BatchItem)) != hipSuccess) { p.b_items = nullptr; return WF_E_NOMEM; }
+    if (hipMemcpy(p.b_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) != hipSuccess)
+      return WF_E_DEVICE;
+    p.b_n_items = (int32_t)items.size();
+    if (hipMalloc(&p.b_sel, (size_t)sel_words * sizeof(uint32_t)) != hipSuccess) { p.b_sel = nullptr; return WF_E_NOMEM; }
+    const size_t bw = (size_t)std::max<int64_t>(bnd_words, 1);
+    if (hipMalloc(&p.b_bnd, bw * sizeof(uint64_t)) != hipSuccess) { p.b_bnd = nullptr; return WF_E_NOMEM; }
+    // tag 0 never equals a launch epoch, so zeroed words read as "not yet written"
+    if (hipMemset(p.b_bnd, 0, bw * sizeof(uint64_t)) != hipSuccess) return WF_E_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+  }
+  p.b_k = K;
+  return WF_OK;
+}
+
+// Rebuilds the forward instance table for checkpoint spacing K (the checkpoint offsets
+// depend on it).  Drains the device first: a queued replay may still read the old table.
+int ensure_fwd_ckpt(wf_plan& p, int32_t K) {
+  if (p.ck_k == K) return WF_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+  if (p.exec) {
+    (void)hipGraphExecDestroy(p.exec);
+    p.exec = nullptr;
+  }
+  return upload_work(p, p.rows, K);
 }
 
 }  // namespace
@@ -311,7 +419,7 @@ int wf_plan_create(wf_plan** out, int dtype, int32_t batch, const int64_t* m, co
     std::vector<BatchInst> inst;
     std::vector<BatchItem> items;
     size_t words = 0;
-    build_work(*p, 1, inst, items, words);
+    build_work(*p, 1, 0, inst, items, words);
     if (items.size() >= (size_t)INT32_MAX) {
       delete p;
       return WF_E_ARG;
@@ -347,7 +455,7 @@ int wf_plan_create(wf_plan** out, int dtype, int32_t batch, const int64_t* m, co
     }
   }
   p->tile = want_tile;
-  rc = upload_work(*p, want_rows);
+  rc = upload_work(*p, want_rows, 0);
   if (rc == WF_OK && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
     p->cap = nullptr;
     rc = WF_E_DEVICE;
@@ -377,19 +485,41 @@ int wf_plan_config(const wf_plan* plan, int32_t* tile, int32_t* rows) {
   return WF_OK;
 }
 
-int wf_batch_forward(wf_plan* plan, const void* C, void* D, void* scores, void* stream) {
+int64_t wf_plan_ckpt_elems(const wf_plan* plan, int32_t ckpt_k) {
+  if (!plan || ckpt_k < 0 || ckpt_k > 4096) return -1;
+  return ckpt_layout(*plan, ckpt_k, nullptr);
+}
+
+int wf_plan_ckpt_offsets(const wf_plan* plan, int32_t ckpt_k, int64_t* offsets) {
+  if (!plan || !offsets || ckpt_k < 0 || ckpt_k > 4096) return WF_E_ARG;
+  std::vector<int64_t> ck;
+  ckpt_layout(*plan, ckpt_k, &ck);
+  std::memcpy(offsets, ck.data(), ck.size() * sizeof(int64_t));
+  return WF_OK;
+}
+
+int wf_batch_forward_ckpt(wf_plan* plan, const void* C, void* D, void* scores, void* ckpt, int32_t ckpt_k,
+                          void* stream) {
   if (!plan || !C || !scores) return WF_E_ARG;
+  if (ckpt_k < 0 || ckpt_k > 4096) return WF_E_ARG;
+  if (ckpt_k == 0 && ckpt != nullptr) return WF_E_ARG;
+  if (ckpt_k > 0 && ckpt == nullptr && ckpt_layout(*plan, ckpt_k, nullptr) > 0) return WF_E_ARG;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
   if (dev != plan->dev) return WF_E_ARG;
+  if (ckpt_k == 0) ckpt = nullptr;
+  if (ckpt) {
+    const int rc = ensure_fwd_ckpt(*plan, ckpt_k);
+    if (rc != WF_OK) return rc;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) return WF_E_DEVICE;
   if (cs == hipStreamCaptureStatusActive) {
     // the caller is building a graph of its own: record the launch into it
-    return launch_plan(*plan, C, D, scores, s) == hipSuccess ? WF_OK : WF_E_DEVICE;
+    return launch_plan(*plan, C, D, scores, ckpt, s) == hipSuccess ? WF_OK : WF_E_DEVICE;
   }
-  if (!plan->exec || plan->g_C != C || plan->g_D != D || plan->g_scores != scores) {
+  if (!plan->exec || plan->g_C != C || plan->g_D != D || plan->g_scores != scores || plan->g_ckpt != ckpt) {
     if (plan->exec) {
       // an earlier replay may still be queued on some stream
       if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
@@ -398,7 +528,7 @@ int wf_batch_forward(wf_plan* plan, const void* C, void* D, void* scores, void* 
     }
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return WF_E_DEVICE;
-    const hipError_t le = launch_plan(*plan, C, D, scores, plan->cap);
+    const hipError_t le = launch_plan(*plan, C, D, scores, ckpt, plan->cap);
     const hipError_t ce = hipStreamEndCapture(plan->cap, &g);
     if (le != hipSuccess || ce != hipSuccess || !g) {
       if (g) (void)hipGraphDestroy(g);
@@ -413,8 +543,55 @@ int wf_batch_forward(wf_plan* plan, const void* C, void* D, void* scores, void* 
     plan->g_C = C;
     plan->g_D = D;
     plan->g_scores = scores;
+    plan->g_ckpt = ckpt;
   }
   return hipGraphLaunch(plan->exec, s) == hipSuccess ? WF_OK : WF_E_DEVICE;
+}
+
+int wf_batch_forward(wf_plan* plan, const void* C, void* D, void* scores, void* stream) {
+  return wf_batch_forward_ckpt(plan, C, D, scores, nullptr, 0, stream);
+}
+
+int wf_batch_backward(wf_plan* plan, const void* C, const void* ckpt, int32_t ckpt_k, const void* D,
+                      const void* g_scores, const void* g_D, void* g_C, void* stream) {
+  if (!plan) return WF_E_ARG;
+  if (plan->dtype != WF_F32 && plan->dtype != WF_F64) return WF_E_UNSUPPORTED;
+  if (!C || !g_C) return WF_E_ARG;
+  if (ckpt_k < 0 || ckpt_k > 4096) return WF_E_ARG;
+  // exactly one source of the band top rows: the checkpoint grids or the saved tables
+  if (ckpt_k > 0 ? (D != nullptr || (ckpt == nullptr && ckpt_layout(*plan, ckpt_k, nullptr) > 0))
+                 : (D == nullptr || ckpt != nullptr))
+    return WF_E_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  if (dev != plan->dev) return WF_E_ARG;
+  int rc = ensure_bwd(*plan, ckpt_k);
+  if (rc != WF_OK) return rc;
+  BwdBatchArgs b;
+  b.C = C;
+  b.top = ckpt_k > 0 ? ckpt : D;
+  b.ckpt_k = ckpt_k;
+  b.n_items = plan->b_n_items;
+  b.gD = g_D;
+  b.gscores = g_scores;
+  b.gC = g_C;
+  b.inst = plan->b_inst;
+  b.items = plan->b_items;
+  b.sel = plan->b_sel;
+  b.bnd = plan->b_bnd;
+  b.ctl = plan->ctl;
+  // the reverse tile of the batch's largest instance
+  int32_t big = 0;
+  for (int32_t i = 1; i < plan->batch; ++i)
+    if (plan->m[i] * plan->n[i] > plan->m[big] * plan->n[big]) big = i;
+  const int tile = pick_tile(plan->dtype, plan->m[big], plan->n[big], true);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the recompute's workgroups are small (two waves, half of a CU's LDS): two per CU
+  if (launch_select_batch(plan->dtype, b, std::min(b.n_items, 2 * plan->num_cus), s) != hipSuccess)
+    return WF_E_DEVICE;
+  if (launch_adjoint_batch(plan->dtype, tile, b, std::min(b.n_items, plan->num_cus), s) != hipSuccess)
+    return WF_E_DEVICE;
+  return WF_OK;
 }
 
 }  // extern "C"

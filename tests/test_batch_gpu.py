@@ -142,17 +142,14 @@ def test_autotuner_picks_an_allowed_config_and_caches_it(tmp_path, monkeypatch):
 
 def test_ragged_512_workload(oracle_mod):
     """The 512-instance workload (m, n uniform in [64, 2048], seed 3) with the autotuned
-    configuration: every score, and the full tables of a sample of 24 instances, against
-    the float32 oracle."""
+    configuration: every instance's full table and score against the float32 oracle."""
     ms, ns, mats = inputs.ragged_batch_f32()
     plan = wf.Plan(ms, ns)
     C = plan.pack([x.to(DEV) for x in mats])
     scores, D = plan.forward(C, table=True)
     wf.last_async_error()
-    sample = list(range(0, 512, 23))[:24]
-    check_instances(oracle_mod, plan, mats, scores, D, "f32", which=sample)
-    ref = np.array([oracle_mod.score(x.numpy(), "f32") for x in mats], dtype=np.float32)
-    assert np.array_equal(scores.cpu().numpy(), ref)
+    del C
+    check_instances(oracle_mod, plan, mats, scores, D, "f32")
 
 
 def test_plan_argument_errors():

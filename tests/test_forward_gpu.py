@@ -152,3 +152,35 @@ def test_blocked_cells(oracle_mod):
     C[0:95, 80] = float("inf")
     D, _, _ = gpu_forward(C)
     assert torch.equal(D, oracle_d(oracle_mod, C, "f32"))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64, torch.int32])
+@pytest.mark.parametrize("shape", [(40000, 200), (20000, 130)])
+def test_more_bands_than_cus(oracle_mod, shape, dtype):
+    """Tall matrices with more 64-row bands than compute units (625 and 313 bands): every
+    workgroup sweeps several bands in turn, each waiting on a band another workgroup (or
+    itself, earlier) swept; the table and the K = 64 checkpoint grid against the oracle."""
+    m, n = shape
+    if dtype == torch.int32:
+        C = inputs.integers(m, n, seed=m, lo=-1000, hi=1000)
+        ref = oracle_d(oracle_mod, C.to(torch.int64), "i64").to(torch.int32)
+    else:
+        C = inputs.uniform(m, n, seed=m, dtype=dtype)
+        ref = oracle_d(oracle_mod, C, "f32" if dtype == torch.float32 else "f64")
+    for tile in (16, 64):
+        D, score, ck = gpu_forward(C, tile, ckpt_k=64)
+        assert torch.equal(D, ref), f"tile {tile}"
+        assert score.item() == ref[-1, -1].item()
+        nb = (m + 63) // 64
+        q = (n + 63) // 64
+        rows = ref[63:64 * (nb - 1):64, :].reshape(-1)
+        cols = ref[:, 63:64 * (q - 1):64].t().reshape(-1)
+        assert torch.equal(ck, torch.cat([rows, cols]))
+
+
+def test_wide_single_band_and_tall_single_column(oracle_mod):
+    """Extreme aspect ratios: one band of 200000 columns, and 100000 rows of one column."""
+    for m, n in ((64, 200000), (100000, 1)):
+        C = inputs.normal_clipped(m, n, seed=m + n)
+        D, score, _ = gpu_forward(C)
+        assert torch.equal(D, oracle_d(oracle_mod, C, "f32")), (m, n)
