@@ -11,9 +11,13 @@ Workload: one 16384 x 16384 float32 instance, values normal(0,1) clipped to [-4,
   3. wf_reverse: the reverse sweep with g_score = 1 (the score's gradient).
 (2 and 3 together are wf_backward.)  Prints ONE JSON line: cells/s of the step (value),
 per-sweep cells/s and effective HBM rates (3 m n sizeof(elem) per sweep), per-kernel
-algorithmic HBM rates measured with HIP events on the launch stream, the roofline entry of
-the kernel that takes the longest, and the CPU oracle timed on a bounded sample on this
-host.
+method-byte HBM rates measured with HIP events on the launch stream (the selection
+bit-planes passed from the recompute to the reverse sweep are reported apart, as
+intermediate traffic), the roofline entry of the kernel that takes the longest, the CPU
+oracle timed on a bounded sample on this host (the whole matrix when it fits the budget),
+and the error of this run's table, score and gradient against that oracle.  Also measured,
+as extra keys: the ragged batch (512 instances, one graph replay) and the batched
+differentiable sweep (64 instances of 2048 x 2048, forward with checkpoints + adjoint).
 """
 from __future__ import annotations
 
@@ -46,7 +50,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=16384)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--no-batch", action="store_true", help="skip the ragged-batch measurement")
+    p.add_argument("--no-batch", action="store_true", help="skip the ragged-batch and batched-adjoint measurements")
     p.add_argument("--calib-copy", action="store_true",
                    help="first run one plain device copy of m*n elements (HBM counter calibration)")
     return p.parse_args()
@@ -186,6 +190,55 @@ def batch_rate(steps: int, warmup: int):
     return out
 
 
+def c5_rate(steps: int, warmup: int):
+    """The batched differentiable sweep: 64 instances of 2048 x 2048 float32 uniform [0,1)
+    (seed 4), one plan; a step is the batched forward (scores and every instance's checkpoint
+    grid, K = 64) and the batched adjoint of the sum of the scores from those grids, each
+    timed with HIP events on the launch stream."""
+    import torch
+
+    import paper_2510_27351_amd as wf
+    from paper_2510_27351_amd import inputs
+
+    C3, _ = inputs.batch_2048_f32()
+    B, m, n = C3.shape
+    plan = wf.Plan([m] * B, [n] * B, offsets=[b * m * n for b in range(B)])
+    C = C3.reshape(-1).cuda()
+    del C3
+    scores = torch.empty(B, device=C.device)
+    ones = torch.ones(B, device=C.device)
+    ck = torch.empty(plan.ckpt_elems(CKPT_K), device=C.device)
+    gC = torch.empty_like(C)
+    for _ in range(max(warmup, 1)):
+        plan.forward_ckpt(C, CKPT_K, scores=scores, ckpt=ck)
+        plan.backward(C, g_scores=ones, ckpt=ck, ckpt_k=CKPT_K, g_C=gC)
+    wf.last_async_error()
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        plan.forward_ckpt(C, CKPT_K, scores=scores, ckpt=ck)
+        ev[k][1].record(stream)
+        plan.backward(C, g_scores=ones, ckpt=ck, ckpt_k=CKPT_K, g_C=gC)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wf.last_async_error()
+    f_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    b_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    cells = B * m * n
+    eff = lambda t: 3 * cells * 4 / (t * 1e-3) / 1e9  # noqa: E731
+    out = {"workload": f"{B} instances of {m}x{n} float32 uniform [0,1) (seed 4); forward writes scores and "
+                       f"checkpoint grids (K={CKPT_K}), adjoint of sum(scores) from the grids; one plan",
+           "cells": cells, "tile": plan.tile, "rows": plan.rows,
+           "fwd": {"ms": f_ms, "cells_per_s": cells / (f_ms * 1e-3), "effective_GBps": eff(f_ms)},
+           "adjoint": {"ms": b_ms, "cells_per_s": cells / (b_ms * 1e-3), "effective_GBps": eff(b_ms)},
+           "fwd_adjoint": {"ms": f_ms + b_ms, "cells_per_s": cells / ((f_ms + b_ms) * 1e-3),
+                           "effective_GBps": 2 * eff(f_ms + b_ms)}}
+    plan.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -312,6 +365,7 @@ def main():
         b = batch_rate(K, args.warmup)
         b["ratio_single_over_batch"] = (cells / (fwd_ms * 1e-3)) / b["cells_per_s"]
         out["batch"] = b
+        out["c5"] = c5_rate(K, args.warmup)
     if not args.no_cpu:
         base, oracle64 = cpu_baseline(C_cpu)
         out["cpu_baseline"] = base
