@@ -111,3 +111,152 @@ def test_pins_catch_planted_mistakes(name):
     x = mutated(a, b, c, d)
     ref = np.linalg.solve(tridiag.dense(a, b, c), d)
     assert np.max(np.abs(x - ref)) > 1e-6, name
+
+
+# ------------------------------------------------------------------------------------------
+# The partition method, stage by stage (tridiag.interface_system / back_solve /
+# partition_solve): pinned to exact rational arithmetic, to the dense solve, and to the
+# properties the paper states for the interface system.
+
+from fractions import Fraction
+
+
+def _rational_system(N, seed):
+    """A diagonally dominant system with small-integer-ratio rational entries."""
+    rng = np.random.default_rng(seed)
+    a = [Fraction(int(v), 4) for v in rng.integers(-4, 5, N)]
+    c = [Fraction(int(v), 4) for v in rng.integers(-4, 5, N)]
+    a[0] = Fraction(0)
+    c[N - 1] = Fraction(0)
+    b = [(abs(a[i]) + abs(c[i]) + 1 + Fraction(int(rng.integers(0, 8)), 8)) * (1 if rng.random() < 0.5 else -1)
+         for i in range(N)]
+    d = [Fraction(int(v), 3) for v in rng.integers(-9, 10, N)]
+    return a, b, c, d
+
+
+def _exact_residual_is_zero(a, b, c, d, x):
+    N = len(b)
+    for i in range(N):
+        s = b[i] * x[i]
+        if i > 0:
+            s += a[i] * x[i - 1]
+        if i < N - 1:
+            s += c[i] * x[i + 1]
+        if s != d[i]:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("N,ms", [(2, [2]), (3, [2]), (13, [4]), (13, [3]), (17, [5]), (40, [4, 3]),
+                                  (41, [6, 4, 2]), (64, [8, 10, 4]), (9, [9]), (9, [20])])
+def test_partition_exact_in_rationals(N, ms):
+    """In exact arithmetic the method returns the exact solution: A x = d holds exactly."""
+    a, b, c, d = _rational_system(N, seed=N * 7 + len(ms))
+    x = tridiag.partition_solve(a, b, c, d, ms)
+    assert all(isinstance(v, Fraction) for v in x)
+    assert _exact_residual_is_zero(a, b, c, d, x)
+
+
+def test_partition_interface_exact_in_rationals():
+    """Every interface equation holds exactly for the exact solution, and the interface
+    system's own solution is the full solution at the interface unknowns (section on the
+    three stages: solving the interface system finds some of the unknowns)."""
+    a, b, c, d = _rational_system(23, seed=5)
+    x = tridiag.thomas(a, b, c, d)
+    assert _exact_residual_is_zero(a, b, c, d, x)
+    A, B, C, D = tridiag.interface_system(a, b, c, d, 5)
+    parts = tridiag.partition_sizes(23, 5)
+    zx = []
+    for s, L in parts:
+        zx += [x[s], x[s + L - 1]]
+    assert _exact_residual_is_zero(A, B, C, D, zx)
+    assert tridiag.thomas(A, B, C, D) == zx
+
+
+@pytest.mark.parametrize("N,m,want", [
+    (10, 5, [(0, 5), (5, 5)]), (11, 5, [(0, 5), (5, 6)]), (12, 5, [(0, 5), (5, 5), (10, 2)]),
+    (2, 2, [(0, 2)]), (3, 2, [(0, 3)]), (5, 8, [(0, 5)]), (7, 3, [(0, 3), (3, 4)])])
+def test_partition_sizes(N, m, want):
+    assert tridiag.partition_sizes(N, m) == want
+
+
+def test_partition_sizes_rejects():
+    with pytest.raises(ValueError):
+        tridiag.partition_sizes(1, 4)
+    with pytest.raises(ValueError):
+        tridiag.partition_sizes(10, 1)
+
+
+@pytest.mark.parametrize("N,ms", [(1, [4]), (2, [2]), (100, [4]), (1000, [32]), (1001, [32]), (999, [7, 10]),
+                                  (5000, [64, 10, 16]), (4097, [16, 10, 8, 4])])
+def test_partition_matches_dense_solve(N, ms):
+    a, b, c, d = _system(N, seed=200 + N)
+    x = tridiag.partition_solve(a, b, c, d, ms)
+    ref = np.linalg.solve(tridiag.dense(a, b, c), d)
+    assert np.max(np.abs(x - ref)) <= 1e-13
+
+
+def test_interface_system_is_diagonally_dominant():
+    """The paper: the interface system is tridiagonal, and diagonally dominant when the
+    initial one is.  Checked on random dominant systems, every level of a recursion."""
+    a, b, c, d = _system(6000, seed=11)
+    for lvl, (A, B, C, D) in enumerate(tridiag.partition_levels(a, b, c, d, [32, 10, 8])):
+        A, B, C = (np.asarray(v, dtype=np.float64) for v in (A, B, C))
+        assert A[0] == 0.0 and C[-1] == 0.0, lvl
+        assert np.all(np.abs(B) > np.abs(A) + np.abs(C)), lvl
+
+
+def test_interface_equations_hold_for_the_solution():
+    """Float64: every interface equation's residual at the true solution is at rounding level."""
+    N, m = 3000, 24
+    a, b, c, d = _system(N, seed=12)
+    x = np.linalg.solve(tridiag.dense(a, b, c), d)
+    A, B, C, D = (np.asarray(v, dtype=np.float64) for v in tridiag.interface_system(a, b, c, d, m))
+    z = np.array([x[i] for s, L in tridiag.partition_sizes(N, m) for i in (s, s + L - 1)])
+    r = B * z - D
+    r[1:] += A[1:] * z[:-1]
+    r[:-1] += C[:-1] * z[1:]
+    assert np.max(np.abs(r)) <= 1e-13 * np.max(np.abs(B))
+
+
+def test_partition_with_m_two_keeps_the_rows():
+    """m = 2: no interior rows, so the interface system is the original system itself."""
+    a, b, c, d = _system(50, seed=13)
+    A, B, C, D = tridiag.interface_system(a, b, c, d, 2)
+    assert np.array_equal(np.asarray(A), a) and np.array_equal(np.asarray(B), b)
+    assert np.array_equal(np.asarray(C), c) and np.array_equal(np.asarray(D), d)
+
+
+PARTITION_MUTATIONS = {
+    "down_spike_sign": ("f.append(-w * f[-1])", "f.append(w * f[-1])"),
+    "down_wrong_upper": ("p.append(b[i] - w * c[i - 1])", "p.append(b[i] - w * c[i])"),
+    "up_dropped_rhs_term": ("t = d[i] - w * t", "t = d[i]"),
+    "up_wrong_lower": ("r = b[i] - w * a[i + 1]", "r = b[i] - w * a[i]"),
+    "up_start_row": ("g, r, t = c[e - 1], b[e - 1], d[e - 1]", "g, r, t = c[e - 1], b[e - 1], d[e]"),
+    "back_spike_sign": ("x[i] = (q[j] - f[j] * xs - c[i] * x[i + 1]) / p[j]",
+                        "x[i] = (q[j] + f[j] * xs - c[i] * x[i + 1]) / p[j]"),
+    "interface_lower_from_wrong_row": ("A.append(a[s] if k > 0 else zero)", "A.append(a[s + 1] if k > 0 else zero)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PARTITION_MUTATIONS))
+def test_partition_pins_catch_planted_mistakes(name):
+    """Plausible mistakes planted in a private copy of the stage functions: the exact
+    rational pin and the dense-solve pin must both reject each one."""
+    import inspect
+    import types
+    old, new = PARTITION_MUTATIONS[name]
+    src = inspect.getsource(tridiag)
+    assert src.count(old) == 1, name
+    mod = types.ModuleType("tridiag_mutated")
+    exec(compile(src.replace(old, new), "tridiag_mutated", "exec"), mod.__dict__)
+    a, b, c, d = _rational_system(17, seed=3)
+    try:
+        x = mod.partition_solve(a, b, c, d, [5])
+        assert not _exact_residual_is_zero(a, b, c, d, x), name
+    except ZeroDivisionError:
+        pass
+    a, b, c, d = _system(300, seed=4)
+    x = mod.partition_solve(a, b, c, d, [12])
+    ref = np.linalg.solve(tridiag.dense(a, b, c), d)
+    assert np.max(np.abs(x - ref)) > 1e-8, name
