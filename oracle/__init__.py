@@ -23,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wf_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "tridiag.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SEL_NONE, SEL_NW, SEL_N, SEL_W = 0, 1, 2, 3
@@ -35,7 +36,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+               "-ffp-contract=off", "-o", tmp, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -45,7 +46,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     i64, p = ctypes.c_int64, ctypes.c_void_p
@@ -58,6 +59,22 @@ def _load():
     lib.wfo_backward_f32.argtypes = [i64, i64, p, p, i64, ctypes.c_float, p, i64]
     lib.wfo_backward_f32.restype = None
     lib.wfo_version.restype = ctypes.c_int
+    i32 = ctypes.c_int32
+    for suf in ("f64", "f32"):
+        f = getattr(lib, "tro_thomas_" + suf)
+        f.argtypes = [i64, p, p, p, p, p]
+        f.restype = ctypes.c_int
+        f = getattr(lib, "tro_interface_" + suf)
+        f.argtypes = [i64, i64, p, p, p, p, p, p, p, p]
+        f.restype = None
+        f = getattr(lib, "tro_back_solve_" + suf)
+        f.argtypes = [i64, i64, p, p, p, p, p, p]
+        f.restype = ctypes.c_int
+        f = getattr(lib, "tro_partition_" + suf)
+        f.argtypes = [i64, i32, p, p, p, p, p, p]
+        f.restype = ctypes.c_int
+    lib.tro_subsystems.argtypes = [i64, i64]
+    lib.tro_subsystems.restype = i64
     if lib.wfo_version() != 2:
         raise RuntimeError("stale oracle build")
     _lib = lib

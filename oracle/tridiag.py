@@ -211,3 +211,61 @@ def partition_solve(a, b, c, d, ms):
     for lvl in range(len(ms) - 1, -1, -1):
         z = back_solve(*levels[lvl], ms[lvl], z)
     return np.asarray(z, dtype=np.float64) if as_float else z
+
+
+# ------------------------------------------------------------------------------------------
+# The same stages in plain C (oracle/tridiag.c), for sizes the loops above would take minutes
+# on.  The tests hold them to the functions above bit for bit.
+
+_PREC = {"f64": np.float64, "f32": np.float32}
+
+
+def _c_arrays(vs, precision):
+    t = _PREC[precision]
+    return [np.ascontiguousarray(np.asarray(v), dtype=t) for v in vs]
+
+
+def c_thomas(a, b, c, d, precision: str = "f64") -> np.ndarray:
+    """``thomas`` in C, in float64 or float32 arithmetic."""
+    from oracle import _load
+    a, b, c, d = _c_arrays((a, b, c, d), precision)
+    x = np.empty_like(b)
+    if getattr(_load(), "tro_thomas_" + precision)(len(b), *(v.ctypes.data for v in (a, b, c, d, x))) != 0:
+        raise MemoryError("oracle allocation failed")
+    return x
+
+
+def c_interface_system(a, b, c, d, m: int, precision: str = "f64"):
+    """``interface_system`` in C: the arrays (A, B, C, D)."""
+    from oracle import _load
+    a, b, c, d = _c_arrays((a, b, c, d), precision)
+    P = _load().tro_subsystems(len(b), m)
+    if P < 0:
+        raise ValueError("the partition needs N >= 2 and m >= 2")
+    out = [np.empty(2 * P, dtype=b.dtype) for _ in range(4)]
+    getattr(_load(), "tro_interface_" + precision)(len(b), m, *(v.ctypes.data for v in (a, b, c, d, *out)))
+    return tuple(out)
+
+
+def c_back_solve(a, b, c, d, m: int, z, precision: str = "f64") -> np.ndarray:
+    """``back_solve`` in C."""
+    from oracle import _load
+    a, b, c, d, z = _c_arrays((a, b, c, d, z), precision)
+    x = np.empty_like(b)
+    if getattr(_load(), "tro_back_solve_" + precision)(len(b), m, *(v.ctypes.data for v in (a, b, c, d, z, x))):
+        raise MemoryError("oracle allocation failed")
+    return x
+
+
+def c_partition_solve(a, b, c, d, ms, precision: str = "f64") -> np.ndarray:
+    """``partition_solve`` in C; ms = [m, m_1, .., m_R] ([] = the direct solve)."""
+    import ctypes
+    from oracle import _load
+    a, b, c, d = _c_arrays((a, b, c, d), precision)
+    x = np.empty_like(b)
+    R = len(ms) - 1
+    arr = (ctypes.c_int32 * max(1, len(ms)))(*ms)
+    rc = getattr(_load(), "tro_partition_" + precision)(len(b), R, arr, *(v.ctypes.data for v in (a, b, c, d, x)))
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return x

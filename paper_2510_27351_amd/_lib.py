@@ -1,4 +1,4 @@
-"""ctypes binding of libwf.so (include/wf.h).  Argument marshalling only."""
+"""ctypes binding of libwf.so (include/wf.h, include/tri.h).  Argument marshalling only."""
 from __future__ import annotations
 
 import ctypes
@@ -8,6 +8,7 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "wf.h")
+TRI_HEADER = os.path.join(os.path.dirname(HERE), "include", "tri.h")
 
 WF_F32, WF_F64, WF_I32 = 0, 1, 2
 WF_OK, WF_E_ARG, WF_E_UNSUPPORTED, WF_E_NOMEM, WF_E_DEVICE, WF_E_TIMEOUT = range(6)
@@ -77,6 +78,28 @@ def load():
     lib.wf_fault_inject.restype = ctypes.c_int
     lib.wf_version.argtypes = []
     lib.wf_version.restype = ctypes.c_int
+    # tridiagonal partition solver (include/tri.h)
+    pi32 = ctypes.POINTER(i32)
+    lib.tri_stage1.argtypes = [ctypes.c_int, i32, i64, i32, p, p, p, p, p, p, p, p, p]
+    lib.tri_stage1.restype = ctypes.c_int
+    lib.tri_stage3.argtypes = [ctypes.c_int, i32, i64, i32, p, p, p, p, p, p, p]
+    lib.tri_stage3.restype = ctypes.c_int
+    lib.tri_thomas.argtypes = [ctypes.c_int, i32, i64, p, p, p, p, p, p, p]
+    lib.tri_thomas.restype = ctypes.c_int
+    lib.tri_subsystems.argtypes = [i64, i32]
+    lib.tri_subsystems.restype = i64
+    lib.tri_plan_create.argtypes = [ctypes.POINTER(p), ctypes.c_int, i32, i64, i32, i32, pi32]
+    lib.tri_plan_create.restype = ctypes.c_int
+    lib.tri_plan_config.argtypes = [p, pi32, pi32, pi32, pi64]
+    lib.tri_plan_config.restype = ctypes.c_int
+    lib.tri_solve.argtypes = [p, p, p, p, p, p, p]
+    lib.tri_solve.restype = ctypes.c_int
+    lib.tri_plan_level.argtypes = [p, i32, p, p, p, p, p]
+    lib.tri_plan_level.restype = ctypes.c_int
+    lib.tri_plan_destroy.argtypes = [p]
+    lib.tri_plan_destroy.restype = None
+    lib.tri_predict.argtypes = [ctypes.c_int, i64, pi32, pi32, pi32]
+    lib.tri_predict.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -91,7 +114,7 @@ def check(code: int, what: str) -> None:
 
 
 def declared_symbols(header: str = HEADER) -> list[str]:
-    """Names of the functions declared in include/wf.h."""
+    """Names of the functions declared in a header of include/ (wf.h by default)."""
     text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(wf_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:wf|tri)_[a-z_0-9]+)\s*\(", text)))

@@ -15,13 +15,13 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwf.so")
-SOURCES = ["wf_fwd.hip", "wf_bwd.hip", "wf_api.hip", "wf_plan.hip"]
+SOURCES = ["wf_fwd.hip", "wf_bwd.hip", "wf_api.hip", "wf_plan.hip", "tri.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-fno-fast-math", "-ffp-contract=off", "-Wall", "-Wno-unused-command-line-argument"]
+          "-fno-fast-math", "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt", "-Wall", "-Wno-unused-command-line-argument"]
 
 
 def build(verbose: bool = False) -> str:

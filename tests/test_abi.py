@@ -143,3 +143,74 @@ def test_reverse_rejects_bad_arguments_before_device_work(lib, case):
     rc = lib.wf_reverse(args["dtype"], args["m"], args["n"], args["g_score"], args["g_D"], args["ldgd"],
                         args["g_C"], args["ldgc"], args["stream"])
     assert rc == args["expect"], case
+
+
+# ------------------------------------------------------------------------------------------
+# The tridiagonal solver's entry points (include/tri.h): exported, and argument errors are
+# refused before any device work.
+
+def test_every_tri_symbol_is_exported(lib):
+    names = _lib.declared_symbols(_lib.TRI_HEADER)
+    assert {"tri_stage1", "tri_stage3", "tri_thomas", "tri_solve", "tri_plan_create", "tri_predict"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_tri_subsystems_matches_the_oracle_partition(lib):
+    from oracle import tridiag
+    for N in (2, 3, 4, 5, 9, 10, 11, 100, 101, 4097):
+        for m in (2, 3, 4, 7, 32, 64, 5000):
+            assert lib.tri_subsystems(N, m) == len(tridiag.partition_sizes(N, m)), (N, m)
+    assert lib.tri_subsystems(1, 4) == -1
+    assert lib.tri_subsystems(10, 1) == -1
+
+
+P = 0x1000  # a non-null pointer that no accepted call would reach
+
+
+@pytest.mark.parametrize("args", [
+    (7, 1, 100, 4),      # dtype
+    (1, 0, 100, 4),      # batch
+    (1, 1, 1, 4),        # N < 2
+    (1, 1, 100, 1),      # m < 2
+    (0, 1, 100, 1),
+])
+def test_tri_stage_argument_errors(lib, args):
+    dt, batch, N, m = args
+    assert lib.tri_stage1(dt, batch, N, m, P, P, P, P, P, P, P, P, None) == _lib.WF_E_ARG
+    assert lib.tri_stage3(dt, batch, N, m, P, P, P, P, P, P, None) == _lib.WF_E_ARG
+
+
+def test_tri_null_pointers_and_limits(lib):
+    assert lib.tri_stage1(1, 1, 100, 4, None, P, P, P, P, P, P, P, None) == _lib.WF_E_ARG
+    assert lib.tri_stage1(1, 1, 100, 4, P, P, P, P, P, P, P, None, None) == _lib.WF_E_ARG
+    assert lib.tri_stage3(1, 1, 100, 4, P, P, P, P, None, P, None) == _lib.WF_E_ARG
+    assert lib.tri_thomas(1, 1, 100, P, P, P, P, P, None, None) == _lib.WF_E_ARG
+    assert lib.tri_thomas(1, 1, 0, P, P, P, P, P, P, None) == _lib.WF_E_ARG
+    # a sub-system must fit in one workgroup's LDS
+    assert lib.tri_stage1(1, 1, 100000, 5000, P, P, P, P, P, P, P, P, None) == _lib.WF_E_UNSUPPORTED
+    assert lib.tri_stage1(0, 1, 100000, 9000, P, P, P, P, P, P, P, P, None) == _lib.WF_E_UNSUPPORTED
+    assert lib.tri_solve(None, P, P, P, P, P, None) == _lib.WF_E_ARG
+
+
+def test_tri_plan_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert lib.tri_plan_create(None, 1, 1, 100, 4, 0, None) == _lib.WF_E_ARG
+    assert lib.tri_plan_create(ctypes.byref(h), 7, 1, 100, 4, 0, None) == _lib.WF_E_ARG
+    assert lib.tri_plan_create(ctypes.byref(h), 1, 0, 100, 4, 0, None) == _lib.WF_E_ARG
+    assert lib.tri_plan_create(ctypes.byref(h), 1, 1, 0, 4, 0, None) == _lib.WF_E_ARG
+    assert lib.tri_plan_create(ctypes.byref(h), 1, 1, 100, 1, 0, None) == _lib.WF_E_ARG
+    assert lib.tri_plan_create(ctypes.byref(h), 1, 1, 100, 4, 7, None) == _lib.WF_E_ARG
+    assert lib.tri_plan_create(ctypes.byref(h), 1, 1, 100, 4, -2, None) == _lib.WF_E_ARG
+    bad = (ctypes.c_int32 * 2)(10, 1)
+    assert lib.tri_plan_create(ctypes.byref(h), 1, 1, 100000, 4, 2, bad) == _lib.WF_E_ARG
+    assert lib.tri_plan_create(ctypes.byref(h), 1, 1, 100000, 3000, 0, None) == _lib.WF_E_UNSUPPORTED
+    assert not h.value
+
+
+def test_tri_predict_validation(lib):
+    m, R = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.tri_predict(7, 1000, ctypes.byref(m), ctypes.byref(R), None) == _lib.WF_E_ARG
+    assert lib.tri_predict(1, 0, ctypes.byref(m), ctypes.byref(R), None) == _lib.WF_E_ARG
+    assert lib.tri_predict(1, 1000, ctypes.byref(m), ctypes.byref(R), None) == 0
+    assert m.value >= 2 and 0 <= R.value <= 6

@@ -260,3 +260,50 @@ def test_partition_pins_catch_planted_mistakes(name):
     x = mod.partition_solve(a, b, c, d, [12])
     ref = np.linalg.solve(tridiag.dense(a, b, c), d)
     assert np.max(np.abs(x - ref)) > 1e-8, name
+
+
+# ------------------------------------------------------------------------------------------
+# The C twin of the stages (oracle/tridiag.c), used for the large GPU parity cases: equal to
+# the Python stages bit for bit, in float64 and in float32 (Python loops over np.float32
+# scalars round every operation to float32, as the C float code does).
+
+C_CASES = [(1, []), (2, [2]), (3, [2]), (10, [4]), (11, [5]), (101, [8, 10]), (1000, [16, 10, 4]),
+           (4097, [64]), (20001, [32, 10, 8, 4]), (3000, [37, 3])]
+
+
+def _f32(v):
+    return [np.float32(x) for x in np.asarray(v, dtype=np.float32)]
+
+
+@pytest.mark.parametrize("N,ms", C_CASES)
+def test_c_partition_equals_python_f64(N, ms):
+    a, b, c, d = _system(N, seed=N)
+    assert np.array_equal(tridiag.c_partition_solve(a, b, c, d, ms), tridiag.partition_solve(a, b, c, d, ms))
+
+
+@pytest.mark.parametrize("N,ms", C_CASES)
+def test_c_partition_equals_python_f32(N, ms):
+    a, b, c, d = _system(N, seed=N + 1)
+    want = np.asarray(tridiag.partition_solve(_f32(a), _f32(b), _f32(c), _f32(d), ms), dtype=np.float32)
+    assert np.array_equal(tridiag.c_partition_solve(a, b, c, d, ms, "f32"), want)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("N,m", [(2, 2), (9, 4), (10, 4), (1001, 32), (515, 256)])
+def test_c_stages_equal_python(N, m, precision):
+    a, b, c, d = _system(N, seed=2 * N + m)
+    conv = (lambda v: list(v)) if precision == "f64" else _f32
+    t = np.float64 if precision == "f64" else np.float32
+    want = tridiag.interface_system(conv(a), conv(b), conv(c), conv(d), m)
+    got = tridiag.c_interface_system(a, b, c, d, m, precision)
+    for g, w in zip(got, want):
+        assert np.array_equal(g, np.asarray(w, dtype=t))
+    z = tridiag.c_thomas(*got, precision)
+    assert np.array_equal(z, np.asarray(tridiag.thomas(*(conv(v) for v in got)), dtype=t))
+    x = tridiag.c_back_solve(a, b, c, d, m, z, precision)
+    assert np.array_equal(x, np.asarray(tridiag.back_solve(conv(a), conv(b), conv(c), conv(d), m, conv(z)), dtype=t))
+
+
+def test_c_thomas_equals_solve():
+    a, b, c, d = _system(5000, seed=9)
+    assert np.array_equal(tridiag.c_thomas(a, b, c, d), tridiag.solve(a, b, c, d))
