@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wf_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "tridiag.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "tridiag.c"), os.path.join(_HERE, "softmin.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SEL_NONE, SEL_NW, SEL_N, SEL_W = 0, 1, 2, 3
@@ -73,6 +73,11 @@ def _load():
         f = getattr(lib, "tro_partition_" + suf)
         f.argtypes = [i64, i32, p, p, p, p, p, p]
         f.restype = ctypes.c_int
+    d = ctypes.c_double
+    lib.wfo_soft_forward_f64.argtypes = [i64, i64, p, i64, d, p, i64]
+    lib.wfo_soft_forward_f64.restype = None
+    lib.wfo_soft_backward_f64.argtypes = [i64, i64, p, i64, p, i64, d, p, i64, d, p, i64]
+    lib.wfo_soft_backward_f64.restype = None
     lib.tro_subsystems.argtypes = [i64, i64]
     lib.tro_subsystems.restype = i64
     if lib.wfo_version() != 2:
@@ -138,3 +143,34 @@ def grad(C, gD=None, gscore=1.0, precision: str = "f64"):
     """Convenience: forward for SEL, then the adjoint."""
     D, sel = forward(C, precision if precision != "i64" else "f64")
     return backward(sel, gD, gscore, precision), D
+
+
+# ------------------------------------------------------------------------------------------
+# Smooth variant (softmin.c): the minimum of the three neighbours replaced by the soft minimum
+# of temperature gamma; float64 only.
+
+def soft_forward(C, gamma: float) -> np.ndarray:
+    """D of the soft-min recurrence (float64; C must be finite)."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    if C.ndim != 2 or C.size == 0:
+        raise ValueError("C must be a non-empty 2-D array")
+    if not gamma > 0:
+        raise ValueError("gamma must be positive")
+    m, n = C.shape
+    D = np.empty_like(C)
+    _load().wfo_soft_forward_f64(m, n, _ptr(C), n, float(gamma), _ptr(D), n)
+    return D
+
+
+def soft_backward(C, D, gamma: float, gD=None, gscore: float = 0.0) -> np.ndarray:
+    """gC of L = sum(gD * D) + gscore * D[-1, -1] for the soft-min recurrence (float64)."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    m, n = C.shape
+    if D.shape != (m, n):
+        raise ValueError("D must match C")
+    g = None if gD is None else np.ascontiguousarray(gD, dtype=np.float64)
+    gC = np.empty_like(C)
+    _load().wfo_soft_backward_f64(m, n, _ptr(C), n, _ptr(D), n, float(gamma), _ptr(g) if g is not None else None,
+                                  n, float(gscore), _ptr(gC), n)
+    return gC
