@@ -74,6 +74,23 @@ enum {
 int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void* D,
                int64_t ldd, void* score, void* ckpt, int32_t ckpt_k, void* stream);
 
+/*
+ * wf_forward for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, checks and results
+ * as wf_forward; it calls no allocating routine.  Its launch control block and handoff words
+ * live in a fixed 32 MiB device array of the library (one copy per GPU, held until the
+ * process ends) instead of the growable workspace, so the shapes it takes are bounded:
+ * (bands - 1) * n * w <= 4194272 handoff words, with bands = ceil(m / 64) and w = 2 for
+ * WF_F64, else 1 (16384 x 16384 float32 fits, 16384 x 16384 float64 does not); larger shapes
+ * return WF_E_UNSUPPORTED before any device work.  A one-thread preparation kernel runs before
+ * the sweep on 'stream'.  Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (streams not ordered with each other) race on it and must not be issued; calls
+ * ordered on one stream are fine, eager or captured.  A bounded wait that expires is reported
+ * by wf_last_async_error, as for wf_forward.
+ */
+int wf_forward_noalloc(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void* D,
+                       int64_t ldd, void* score, void* ckpt, int32_t ckpt_k, void* stream);
+
 /* Number of elements of the checkpoint grid written by wf_forward (0 when ckpt_k == 0, or
  * -1 on invalid sizes). */
 int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k);

@@ -60,6 +60,8 @@ def load():
     lib.wf_batch_backward.restype = ctypes.c_int
     lib.wf_plan_destroy.argtypes = [p]
     lib.wf_plan_destroy.restype = None
+    lib.wf_forward_noalloc.argtypes = [ctypes.c_int, i64, i64, p, i64, p, i64, p, p, i32, p]
+    lib.wf_forward_noalloc.restype = ctypes.c_int
     lib.wf_ckpt_elems.argtypes = [i64, i64, i32]
     lib.wf_ckpt_elems.restype = i64
     lib.wf_set_tile.argtypes = [i32]

@@ -105,6 +105,57 @@ int64_t nbands(int64_t m) { return (m + kBand - 1) / kBand; }
 
 int pick_tile(int dtype, int64_t m, int64_t n, bool reverse) { return choose_tile(dtype, m, n, reverse); }
 
+// ---------------------------------------------------------------------------------------
+// Scratch of the allocation-free forward sweep (wf_forward_noalloc): a file-scope device
+// array, one copy per GPU, held until the process ends.  Bytes [0, 256) are the launch
+// control block; the tagged handoff words follow.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol): each device's address
+// comes from hipGetSymbolAddress, taken once per device with that device current.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)32 << 20;  // 32 MiB
+constexpr size_t kScratchCtl = 256;                  // control block, then handoff words
+constexpr size_t kScratchWords = (kScratchBytes - kScratchCtl) / sizeof(uint64_t);
+
+__device__ __align__(256) uint64_t scratch[kScratchBytes / sizeof(uint64_t)];
+
+struct ScratchDev {
+  bool ready = false;
+  char* ptr = nullptr;  // this device's copy of 'scratch'
+  int num_cus = 0;
+};
+std::vector<ScratchDev> g_scratch;  // per device, guarded by g_mu
+
+// The current device's scratch: address and CU count, looked up on the first call on it.
+int scratch_of(int dev, ScratchDev* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
+  ScratchDev& sd = g_scratch[dev];
+  if (!sd.ready) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return WF_E_DEVICE;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      return WF_E_DEVICE;
+    sd.ptr = static_cast<char*>(p);
+    sd.num_cus = cus;
+    sd.ready = true;
+  }
+  *out = sd;
+  return WF_OK;
+}
+
+// The control block starts zeroed with the array; a launch needs a non-zero epoch (tag 0 is
+// what never-written handoff words carry).  Enqueued before every sweep, so that the order
+// of calls, eager or captured in a graph, never matters; later launches advance the epoch
+// themselves.
+__global__ void scratch_prepare(Control* ctl) {
+  if (threadIdx.x == 0 && __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+    __hip_atomic_store(&ctl->epoch, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
 }  // namespace wf
 
 using namespace wf;
@@ -229,6 +280,55 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
   const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
   const int tile = choose_tile(dtype, m, n, false);
   hipError_t e = launch_forward(dtype, tile, a, grid, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? WF_OK : WF_E_DEVICE;
+}
+
+int wf_forward_noalloc(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void* D, int64_t ldd,
+                       void* score, void* ckpt, int32_t ckpt_k, void* stream) {
+  const int es = elem_size(dtype);
+  if (es == 0) return WF_E_ARG;
+  if (m < 1 || n < 1 || n > (int64_t)1 << 31 || m > (int64_t)1 << 40) return WF_E_ARG;
+  if (m > INT64_MAX / n) return WF_E_ARG;
+  if (!C || !score || ldc < n) return WF_E_ARG;
+  if (D && ldd < n) return WF_E_ARG;
+  if (ckpt_k < 0 || ckpt_k > 4096) return WF_E_ARG;
+  if (ckpt_k == 0 && ckpt != nullptr) return WF_E_ARG;
+  if (ckpt_k > 0 && ckpt == nullptr && wf_ckpt_elems(m, n, ckpt_k) > 0) return WF_E_ARG;
+  if ((m - 1) > INT64_MAX / ldc) return WF_E_ARG;
+  if (ldc > kMaxLd / es || (D && ldd > kMaxLd / es)) return WF_E_UNSUPPORTED;
+  const int64_t band_rows = forward_band_rows(dtype);
+  const int64_t nb = (m + band_rows - 1) / band_rows;
+  if (nb > 0x7fffffff) return WF_E_ARG;
+  // the handoff words of every band boundary must fit in the scratch array
+  const int64_t words = (nb - 1) * words_per_elem(dtype);
+  if (words > 0 && n > (int64_t)kScratchWords / words) return WF_E_UNSUPPORTED;
+
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  ScratchDev sd;
+  int rc = scratch_of(dev, &sd);
+  if (rc != WF_OK) return rc;
+  Control* ctl = reinterpret_cast<Control*>(sd.ptr);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(scratch_prepare, dim3(1), dim3(64), 0, st, ctl);
+  if (hipGetLastError() != hipSuccess) return WF_E_DEVICE;
+
+  FwdArgs a;
+  a.C = C;
+  a.D = D;
+  a.score = score;
+  a.ckpt = ckpt;
+  a.ldc = ldc;
+  a.ldd = D ? ldd : n;
+  a.m = m;
+  a.n = n;
+  a.ckpt_k = ckpt_k;
+  a.nb = (int32_t)nb;
+  a.ctl = ctl;
+  a.bnd = reinterpret_cast<uint64_t*>(sd.ptr + kScratchCtl);
+  a.trace = nullptr;
+  const int grid = (int)std::min<int64_t>(nb, sd.num_cus);
+  hipError_t e = launch_forward(dtype, choose_tile(dtype, m, n, false), a, grid, st);
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
 
@@ -424,13 +524,22 @@ int wf_last_async_error(void* stream) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (dev < (int)g_ws.size()) ctl = g_ws[dev].ctl;
   }
-  if (!ctl) return WF_OK;
-  uint32_t err = 0;
-  if (hipMemcpy(&err, &ctl->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return WF_E_DEVICE;
-  if (err == 0) return WF_OK;
-  const uint32_t zero = 0;
-  if (hipMemcpy(&ctl->err, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return WF_E_DEVICE;
-  return WF_E_TIMEOUT;
+  Control* sctl = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev < (int)g_scratch.size() && g_scratch[dev].ready) sctl = reinterpret_cast<Control*>(g_scratch[dev].ptr);
+  }
+  uint32_t any = 0;
+  for (Control* c : {ctl, sctl}) {
+    if (!c) continue;
+    uint32_t err = 0;
+    if (hipMemcpy(&err, &c->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return WF_E_DEVICE;
+    if (err == 0) continue;
+    any |= err;
+    const uint32_t zero = 0;
+    if (hipMemcpy(&c->err, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return WF_E_DEVICE;
+  }
+  return any ? WF_E_TIMEOUT : WF_OK;
 }
 
 }  // extern "C"
