@@ -272,6 +272,36 @@ int wf_last_async_error(void* stream);
  */
 int wf_fault_inject(int32_t mode);
 
+/*
+ * Smooth variant of the recurrence: the minimum replaced by the soft minimum of temperature
+ * gamma > 0,
+ *     D[i][j] = C[i][j] - gamma log( exp(-D[i-1][j-1]/gamma) + exp(-D[i-1][j]/gamma)
+ *                                    + exp(-D[i][j-1]/gamma) ),
+ * same boundary as above (the soft dynamic-time-warping recursion; gamma -> 0 gives the
+ * min-plus table).  D[i][j] is -gamma log of the sum over all monotone paths from (0,0) to
+ * (i,j) of exp(-path cost/gamma), so the table is smooth in C and its gradient is exact
+ * (no selections, no ties).  C must be finite.  WF_F32 or WF_F64; the exponentials and
+ * logarithms are the device's base-2 functions, so results agree with a float64 evaluation
+ * to within rounding, not bit for bit.
+ *
+ * wf_soft_forward writes the full table D (m x n, ldd >= n; required, the adjoint reads it)
+ * and score = D[m-1][n-1].
+ * wf_soft_backward writes g_C = dL/dC for L = sum(g_D * D) + g_score * score from C and the
+ * forward's D:
+ *     A[i][j] = g_D[i][j] + [i=m-1, j=n-1] g_score + w(i+1,j+1) A[i+1][j+1]
+ *             + w(i+1,j) A[i+1][j] + w(i,j+1) A[i][j+1],  g_C = A,
+ * with w(s) = exp((D(s) - C(s) - D[i][j]) / gamma) the derivative of successor s's soft
+ * minimum with respect to D[i][j].  g_score (one element) and g_D may be NULL (= 0).
+ * Both are persistent band pipelines on the device workspace like wf_forward (same stream
+ * ordering rules, bounded waits reported by wf_last_async_error).  gamma must be positive
+ * and finite (WF_E_ARG otherwise); WF_I32 returns WF_E_UNSUPPORTED.
+ */
+int wf_soft_forward(int dtype, int64_t m, int64_t n, double gamma, const void* C, int64_t ldc,
+                    void* D, int64_t ldd, void* score, void* stream);
+int wf_soft_backward(int dtype, int64_t m, int64_t n, double gamma, const void* C, int64_t ldc,
+                     const void* D, int64_t ldd, const void* g_score, const void* g_D,
+                     int64_t ldgd, void* g_C, int64_t ldgc, void* stream);
+
 /* Static, human-readable name of an error code. */
 const char* wf_error_string(int code);
 

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import WfError  # noqa: F401
 
 __all__ = ["forward", "backward", "sweep", "WfFunction", "Plan", "ckpt_elems", "set_tile", "predict_tile",
-           "last_async_error", "WfError", "BAND"]
+           "last_async_error", "WfError", "BAND", "soft_forward", "soft_backward", "soft_sweep", "SoftWfFunction"]
 
 BAND = 64  # rows per band of the device sweep (= wavefront size)
 
@@ -210,6 +210,71 @@ def sweep(C: torch.Tensor, table: bool = False, ckpt_k: int = 64):
     if not table and not 1 <= ckpt_k <= 4096:
         raise ValueError("ckpt_k must be in [1, 4096]")
     return WfFunction.apply(C, table, ckpt_k)
+
+
+# ------------------------------------------------------------------------------------------
+# Smooth variant: the minimum replaced by the soft minimum of temperature gamma.
+
+def soft_forward(C: torch.Tensor, gamma: float, D: torch.Tensor | None = None):
+    """Forward sweep of the soft-min recurrence (wf_soft_forward): returns (D, score)."""
+    _check_matrix(C)
+    m, n = C.shape
+    if D is None:
+        D = torch.empty((m, n), dtype=C.dtype, device=C.device)
+    elif D.shape != (m, n) or D.dtype != C.dtype or D.device != C.device or D.stride(1) != 1:
+        raise ValueError("D must match C's shape, dtype and device, row-major")
+    score = torch.empty((), dtype=C.dtype, device=C.device)
+    rc = _lib.load().wf_soft_forward(_dtype_code(C), m, n, float(gamma), C.data_ptr(), C.stride(0), D.data_ptr(),
+                                     D.stride(0), score.data_ptr(), _stream(C.device))
+    _lib.check(rc, "wf_soft_forward")
+    return D, score
+
+
+def soft_backward(C: torch.Tensor, D: torch.Tensor, gamma: float, g_score: torch.Tensor | None = None,
+                  g_D: torch.Tensor | None = None, g_C: torch.Tensor | None = None) -> torch.Tensor:
+    """Adjoint of the soft-min sweep (wf_soft_backward): g_C for L = sum(g_D * D) + g_score * score."""
+    _check_matrix(C)
+    m, n = C.shape
+    for name, t in (("D", D), ("g_D", g_D), ("g_C", g_C)):
+        if t is not None and (t.shape != (m, n) or t.dtype != C.dtype or t.device != C.device or t.stride(1) != 1):
+            raise ValueError(f"{name} must match C's shape, dtype and device, row-major")
+    if g_score is not None:
+        g_score = g_score.to(device=C.device, dtype=C.dtype).reshape(()).contiguous()
+    if g_C is None:
+        g_C = torch.empty((m, n), dtype=C.dtype, device=C.device)
+    rc = _lib.load().wf_soft_backward(_dtype_code(C), m, n, float(gamma), C.data_ptr(), C.stride(0), D.data_ptr(),
+                                      D.stride(0), g_score.data_ptr() if g_score is not None else None,
+                                      g_D.data_ptr() if g_D is not None else None,
+                                      g_D.stride(0) if g_D is not None else n, g_C.data_ptr(), g_C.stride(0),
+                                      _stream(C.device))
+    _lib.check(rc, "wf_soft_backward")
+    return g_C
+
+
+class SoftWfFunction(torch.autograd.Function):
+    """Differentiable soft-min sweep: (D, score) = soft_sweep(C, gamma); the table is saved
+    for the backward, which runs the adjoint sweep on the device."""
+
+    @staticmethod
+    def forward(ctx, C: torch.Tensor, gamma: float):
+        C = C.contiguous()
+        D, score = soft_forward(C, gamma)
+        ctx.save_for_backward(C, D)
+        ctx.gamma = gamma
+        return D, score
+
+    @staticmethod
+    def backward(ctx, g_D, g_score):
+        C, D = ctx.saved_tensors
+        g_D = None if g_D is None else g_D.contiguous()
+        return soft_backward(C, D, ctx.gamma, g_score=g_score, g_D=g_D), None
+
+
+def soft_sweep(C: torch.Tensor, gamma: float):
+    """Autograd entry point of the soft-min sweep: (D, score) of an m x n instance."""
+    if C.dim() != 2:
+        raise ValueError("C must be (m, n)")
+    return SoftWfFunction.apply(C, gamma)
 
 
 _PLANS: dict = {}

@@ -62,6 +62,11 @@ def load():
     lib.wf_plan_destroy.restype = None
     lib.wf_forward_noalloc.argtypes = [ctypes.c_int, i64, i64, p, i64, p, i64, p, p, i32, p]
     lib.wf_forward_noalloc.restype = ctypes.c_int
+    dbl = ctypes.c_double
+    lib.wf_soft_forward.argtypes = [ctypes.c_int, i64, i64, dbl, p, i64, p, i64, p, p]
+    lib.wf_soft_forward.restype = ctypes.c_int
+    lib.wf_soft_backward.argtypes = [ctypes.c_int, i64, i64, dbl, p, i64, p, i64, p, p, i64, p, i64, p]
+    lib.wf_soft_backward.restype = ctypes.c_int
     lib.wf_ckpt_elems.argtypes = [i64, i64, i32]
     lib.wf_ckpt_elems.restype = i64
     lib.wf_set_tile.argtypes = [i32]

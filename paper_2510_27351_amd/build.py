@@ -15,7 +15,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwf.so")
-SOURCES = ["wf_fwd.hip", "wf_bwd.hip", "wf_api.hip", "wf_plan.hip", "tri.hip"]
+SOURCES = ["wf_fwd.hip", "wf_bwd.hip", "wf_api.hip", "wf_plan.hip", "wf_soft.hip", "tri.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

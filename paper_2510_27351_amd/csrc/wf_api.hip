@@ -16,6 +16,7 @@
 
 #include "../../include/wf.h"
 #include "wf_internal.h"
+#include "wf_soft.h"
 
 namespace wf {
 namespace {
@@ -467,6 +468,90 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   int rc = wf_select(dtype, m, n, C, ldc, ckpt, ckpt_k, D, ldd, stream);
   if (rc != WF_OK) return rc;
   return wf_reverse(dtype, m, n, g_score, g_D, ldgd, g_C, ldgc, stream);
+}
+
+namespace {
+
+// Checks shared by the two smooth sweeps; fills the sizes of the launch.
+int soft_check(int dtype, int64_t m, int64_t n, double gamma, int64_t* nb) {
+  if (dtype != WF_F32 && dtype != WF_F64) return dtype == WF_I32 ? WF_E_UNSUPPORTED : WF_E_ARG;
+  if (m < 1 || n < 1 || n > (int64_t)1 << 31 || m > (int64_t)1 << 40) return WF_E_ARG;
+  if (m > INT64_MAX / n) return WF_E_ARG;
+  if (!(gamma > 0.0) || !std::isfinite(gamma)) return WF_E_ARG;
+  *nb = nbands(m);
+  if (*nb > 0x7fffffff) return WF_E_ARG;
+  return WF_OK;
+}
+
+}  // namespace
+
+int wf_soft_forward(int dtype, int64_t m, int64_t n, double gamma, const void* C, int64_t ldc, void* D, int64_t ldd,
+                    void* score, void* stream) {
+  int64_t nb = 0;
+  int rc = soft_check(dtype, m, n, gamma, &nb);
+  if (rc != WF_OK) return rc;
+  const int es = elem_size(dtype);
+  if (!C || !D || !score || ldc < n || ldd < n) return WF_E_ARG;
+  if (ldc > kMaxLd / es || ldd > kMaxLd / es) return WF_E_UNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  DeviceWs* ws = nullptr;
+  rc = ensure_ws(dev, (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * words_per_elem(dtype), &ws);
+  if (rc != WF_OK) return rc;
+  SoftArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.C = C;
+  a.D = D;
+  a.score = score;
+  a.ldc = ldc;
+  a.ldd = ldd;
+  a.m = m;
+  a.n = n;
+  a.nb = (int32_t)nb;
+  a.kx = 1.0 / (gamma * std::log(2.0));
+  a.gl = gamma * std::log(2.0);
+  a.ctl = ws->ctl;
+  a.bnd = ws->bnd;
+  const int grid = (int)std::min<int64_t>(nb, 4 * (int64_t)ws->num_cus);
+  return launch_soft_forward(dtype, a, grid, static_cast<hipStream_t>(stream)) == hipSuccess ? WF_OK : WF_E_DEVICE;
+}
+
+int wf_soft_backward(int dtype, int64_t m, int64_t n, double gamma, const void* C, int64_t ldc, const void* D,
+                     int64_t ldd, const void* g_score, const void* g_D, int64_t ldgd, void* g_C, int64_t ldgc,
+                     void* stream) {
+  int64_t nb = 0;
+  int rc = soft_check(dtype, m, n, gamma, &nb);
+  if (rc != WF_OK) return rc;
+  const int es = elem_size(dtype);
+  if (!C || !D || !g_C || ldc < n || ldd < n || ldgc < n) return WF_E_ARG;
+  if (g_D && ldgd < n) return WF_E_ARG;
+  if (ldc > kMaxLd / es || ldd > kMaxLd / es || ldgc > kMaxLd / es || (g_D && ldgd > kMaxLd / es))
+    return WF_E_UNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  DeviceWs* ws = nullptr;
+  rc = ensure_ws(dev, (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * 2 * words_per_elem(dtype), &ws);
+  if (rc != WF_OK) return rc;
+  SoftArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.C = C;
+  a.Din = D;
+  a.gD = g_D;
+  a.gscore = g_score;
+  a.gC = g_C;
+  a.ldc = ldc;
+  a.ldd = ldd;
+  a.ldgd = g_D ? ldgd : n;
+  a.ldgc = ldgc;
+  a.m = m;
+  a.n = n;
+  a.nb = (int32_t)nb;
+  a.kx = 1.0 / (gamma * std::log(2.0));
+  a.gl = gamma * std::log(2.0);
+  a.ctl = ws->ctl;
+  a.bnd = ws->bnd;
+  const int grid = (int)std::min<int64_t>(nb, 4 * (int64_t)ws->num_cus);
+  return launch_soft_backward(dtype, a, grid, static_cast<hipStream_t>(stream)) == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
 
 int wf_trace_enable(int64_t max_bands) {

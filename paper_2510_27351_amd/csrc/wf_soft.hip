@@ -1,0 +1,489 @@
+// Smooth (soft-min) variant of the wavefront recurrence on gfx950 (wf_soft_forward,
+// wf_soft_backward in include/wf.h).
+//
+// The minimum of the north-west, north and west neighbours is replaced by the soft minimum
+// of temperature gamma,  softmin(x) = -gamma log sum_k exp(-x_k / gamma),  evaluated about
+// the smallest argument mn:  softmin = mn - gamma ln2 log2( sum_k 2^((mn - x_k) log2e / gamma) ).
+// The adjoint of  L = sum(gD * D) + gscore * score  is
+//     A[i][j] = gD[i][j] + [last] gscore + w(i+1,j+1) A[i+1][j+1] + w(i+1,j) A[i+1][j]
+//             + w(i,j+1) A[i][j+1],       w(succ) = 2^((V(succ) - D[i][j]) log2e / gamma),
+// with V(succ) = D(succ) - C(succ) the successor's soft minimum, so the weight is the
+// derivative of the successor's soft minimum with respect to D[i][j].  gC = A.
+//
+// Both sweeps are persistent band pipelines like the min-plus ones, in a lighter form: a
+// workgroup of two waves per 64-row band, claimed in order (top-down forward, bottom-up for
+// the adjoint).  The compute wave runs the skewed wavefront (lane r owns band row r; at step
+// t it handles column t - r forward, n - 1 - t + 63 - r backward), taking the lane-shifted
+// neighbour values through DPP and reading its inputs straight from global memory as
+// 16-byte range-checked buffer loads of four consecutive columns, issued two 4-step groups
+// ahead.  The band's edge row goes to the next band as epoch-tagged 64-bit words (the
+// forward's last row; the adjoint's first row as (A, V) pairs); the second wave polls them
+// into an LDS ring that the compute wave reads.  Every wait is bounded.
+#include "wf_common.h"
+#include "wf_soft.h"
+
+namespace wf {
+namespace {
+
+constexpr int kRing = 1024;  // handoff ring: columns
+
+template <typename T>
+struct SoftMath;
+// float: the hardware base-2 exponential and logarithm (v_exp_f32, v_log_f32, about one
+// ulp).  The logarithm's argument is a sum in [1, 3]; an exponential that would be
+// subnormal (a weight below 2^-126) reads as 0, which changes no sum it enters.
+template <>
+struct SoftMath<float> {
+  __device__ static __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
+  __device__ static __forceinline__ float log2_(float x) { return __builtin_amdgcn_logf(x); }
+};
+template <>
+struct SoftMath<double> {
+  __device__ static __forceinline__ double exp2_(double x) { return exp2(x); }
+  __device__ static __forceinline__ double log2_(double x) { return log2(x); }
+};
+
+// Four consecutive columns of one row, as one (float) or two (double) 16-byte transfers.
+template <typename T>
+__device__ __forceinline__ Vec4<T> load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  Vec4<T> v;
+  if constexpr (sizeof(T) == 4) {
+    v = __builtin_bit_cast(Vec4<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  } else {
+    using H = struct alignas(16) { uint32_t w[4]; };
+    H lo = __builtin_bit_cast(H, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    H hi = __builtin_bit_cast(H, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0));
+    uint32_t w[8];
+    for (int q = 0; q < 4; ++q) {
+      w[q] = lo.w[q];
+      w[4 + q] = hi.w[q];
+    }
+    __builtin_memcpy(&v, w, sizeof(v));
+  }
+  return v;
+}
+
+// Four columns col .. col+3 of this lane's row (lane * ld elements into the resource).  A
+// start before the resource (only lane 0 near the left edge of the adjoint's last groups,
+// columns below 0) loads from offset 0 and moves the columns into place; the slots before
+// column 0 hold no data and are never used.
+template <typename T>
+__device__ __forceinline__ Vec4<T> load4_at(__amdgpu_buffer_rsrc_t r, int64_t ld, int lane, int64_t col) {
+  const int64_t e = (int64_t)lane * ld + col;
+  if (e >= 0) return load4<T>(r, (uint32_t)(e * (int64_t)sizeof(T)));
+  const Vec4<T> v = load4<T>(r, 0u);
+  const int sh = (int)-e;  // 1 .. 3
+  Vec4<T> o = v;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o.v[q] = q >= sh ? v.v[q - sh] : v.v[0];
+  return o;
+}
+
+// wave_shl:1 -- lane r receives lane r+1's value; lane 63 keeps 'old'.
+template <typename T>
+__device__ __forceinline__ T shl1_(T src, T old) {
+  auto mv = [](uint32_t s, uint32_t o) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)o, (int)s, 0x130, 0xf, 0xf, false);
+  };
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, mv(__builtin_bit_cast(uint32_t, src), __builtin_bit_cast(uint32_t, old)));
+  } else {
+    const uint64_t s = __builtin_bit_cast(uint64_t, src), o = __builtin_bit_cast(uint64_t, old);
+    const uint64_t lo = mv((uint32_t)s, (uint32_t)o), hi = mv((uint32_t)(s >> 32), (uint32_t)(o >> 32));
+    return __builtin_bit_cast(T, (hi << 32) | lo);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store1(__amdgpu_buffer_rsrc_t r, uint32_t off, T x) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, off, 0, 0);
+  } else {
+    using V2 = __attribute__((ext_vector_type(2))) uint32_t;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, off, 0, 0);
+  }
+}
+
+// Range-checked resource over rows [row0, row0 + rows) of a matrix with leading dimension
+// ld: the last row ends at its n-th element, so nothing past the caller's data is touched.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t band_rsrc(const void* base, int64_t row0, int rows, int64_t ld,
+                                                            int64_t n) {
+  const T* p = static_cast<const T*>(base) + row0 * ld;
+  const int64_t bytes = rows > 0 ? ((int64_t)(rows - 1) * ld + n) * (int64_t)sizeof(T) : 0;
+  return make_rsrc(p, (uint32_t)bytes);
+}
+
+struct alignas(8) SoftShared {
+  uint32_t avail;  // handoff columns in the ring, in the consumer's order
+  uint32_t used;   // columns the compute wave has finished with
+  uint32_t item;
+  uint32_t abort;
+};
+
+// ---------------------------------------------------------------------------------------
+// The poller: fetches the producer band's tagged words, 64 columns per pass from the first
+// one not yet handed over, and hands over the leading run of complete columns.  NV values
+// per column (1 forward, 2 backward), each of W payload words; 'word_at(k)' is the address
+// of the first word of consumer column k.
+template <typename T, int NV, typename WordAt>
+__device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl, int64_t n, uint32_t epoch,
+                                          WordAt word_at) {
+  using E = Elem<T>;
+  constexpr int W = E::W;
+  const int lane = threadIdx.x & 63;
+  uint64_t waited = 0, t0 = 0;
+  uint32_t polls = 0;
+  int64_t u = 0;
+  while (u < n) {
+    // ring slots of columns u .. u+63 are free once the compute wave is past column u+63-kRing
+    const int64_t need = u + 64 - kRing;
+    if (need > 0 && !lds_wait_ge(&sh.used, (uint32_t)need, &sh.abort, ctl, waited)) return false;
+    const int64_t k = u + lane;
+    const bool real = k < n;
+    const uint64_t* src = real ? word_at(k) : reinterpret_cast<const uint64_t*>(ctl) + 4;
+    uint64_t x[NV * W];
+#pragma unroll
+    for (int q = 0; q < NV * W; ++q) x[q] = load_word(src + q);
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < NV * W; ++q) ok = ok && (uint32_t)(x[q] >> 32) == epoch;
+    ok = ok || !real;
+    const uint64_t okm = __ballot(ok);
+    const int run = ~okm == 0 ? 64 : __builtin_ctzll(~okm);
+    const int take = (int)(run < n - u ? run : n - u);
+    if (take == 0) {
+      if (polls == 0) t0 = __builtin_amdgcn_s_memrealtime();
+      __builtin_amdgcn_s_sleep(1);
+      if ((++polls & 63u) == 0u) {
+        if (lds_load(&sh.abort) != 0u || global_aborted(ctl)) return false;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) {
+          raise_timeout(ctl);
+          return false;
+        }
+      }
+      continue;
+    }
+    polls = 0;
+    if (lane < take) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        uint32_t w[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) w[q] = (uint32_t)x[v * W + q];
+        ring[v * kRing + (int)((u + lane) & (kRing - 1))] = E::from_words(w);
+      }
+    }
+    u += take;
+    lds_publish(&sh.avail, (uint32_t)u);
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// Forward.
+
+template <typename T>
+__device__ __forceinline__ T soft_cell(T c, T nw, T nn, T w, T kx, T gl) {
+  using M = SoftMath<T>;
+  using E = Elem<T>;
+  const T mn = E::min3(nw, nn, w);
+  const T s = M::exp2_((mn - nw) * kx) + M::exp2_((mn - nn) * kx) + M::exp2_((mn - w) * kx);
+  const T v = mn - gl * M::log2_(s);
+  return mn < E::inf() ? c + v : E::inf();
+}
+
+template <typename T>
+__device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const SoftArgs& a, int band,
+                                                 uint32_t epoch) {
+  using E = Elem<T>;
+  constexpr int W = E::W;
+  const int lane = threadIdx.x & 63;
+  const int64_t m = a.m, n = a.n;
+  const int64_t row0 = (int64_t)band * kBand;
+  const int rows = (int)(m - row0 < kBand ? m - row0 : kBand);
+  const int64_t i = row0 + lane;
+  const bool live = lane < rows;
+  const auto rc = band_rsrc<T>(a.C, row0, rows, a.ldc, n);
+  const auto rd = band_rsrc<T>(a.D, row0, rows, a.ldd, n);
+  const T kx = (T)a.kx, gl = (T)a.gl;
+  const bool first = band == 0;
+  const bool publish = lane == 63 && band < a.nb - 1;
+  // this lane's column at step t is t - lane; group g covers steps 4g .. 4g+3
+  const int64_t groups = (n + 63 + 3) / 4;
+  auto off_c = [&](int64_t g) -> uint32_t { return (uint32_t)(((int64_t)lane * a.ldc + 4 * g - lane) * sizeof(T)); };
+  auto off_d = [&](int64_t col) -> uint32_t { return (uint32_t)(((int64_t)lane * a.ldd + col) * sizeof(T)); };
+  T X = E::inf(), NW = (first && lane == 0) ? E::zero() : E::inf();
+  Vec4<T> c0 = load4<T>(rc, off_c(0)), c1 = load4<T>(rc, off_c(1));
+  uint64_t waited = 0;
+  for (int64_t g = 0; g < groups; ++g) {
+    const Vec4<T> cg = c0;
+    c0 = c1;
+    c1 = load4<T>(rc, off_c(g + 2));
+    // the top row's columns 4g .. 4g+3 (lane 0's)
+    Vec4<T> top;
+    if (first) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) top.v[q] = E::inf();
+    } else {
+      const int64_t need = 4 * g + 4 < n ? 4 * g + 4 : n;
+      if (need > 4 * g && lds_load(&sh.avail) < (uint32_t)need) {
+        uint32_t seen;
+        if (!lds_wait_value<true, false>(&sh.avail, (uint32_t)need, &sh.abort, a.ctl, waited, seen)) return false;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = 4 * g + q;
+        top.v[q] = col < n ? ring[(int)(col & (kRing - 1))] : E::inf();
+      }
+    }
+    Vec4<T> out;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T N = E::shr1(X, top.v[q]);
+      X = soft_cell<T>(cg.v[q], NW, N, X, kx, gl);
+      NW = N;
+      out.v[q] = X;
+    }
+    // columns 4g - lane .. 4g - lane + 3 of row i
+    const int64_t col0 = 4 * g - lane;
+    if (live) {
+      if (col0 >= 0 && col0 + 3 < n) {
+        if constexpr (sizeof(T) == 4) {
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, out),
+                                                 rd, off_d(col0), 0, 0);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) store1<T>(rd, off_d(col0 + q), out.v[q]);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (col0 + q >= 0 && col0 + q < n) store1<T>(rd, off_d(col0 + q), out.v[q]);
+      }
+      if (i == m - 1 && col0 <= n - 1 && n - 1 <= col0 + 3) static_cast<T*>(a.score)[0] = out.v[n - 1 - col0];
+    }
+    if (publish) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = col0 + q;
+        if (col >= 0 && col < n) {
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+            store_word(a.bnd + ((int64_t)band * n + col) * W + w, tagged(E::word(out.v[q], w), epoch));
+        }
+      }
+    }
+    if (!first && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * g + 4));
+  }
+  return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(128) void soft_fwd_kernel(SoftArgs a) {
+  using E = Elem<T>;
+  __shared__ T ring[kRing];
+  __shared__ SoftShared sh;
+  Control* ctl = a.ctl;
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) sh.abort = 0u;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      sh.avail = 0u;
+      sh.used = 0u;
+    }
+    claim_next(ctl, &sh.item, &sh.abort);
+    const int band = (int)sh.item;
+    if (band >= a.nb || sh.abort != 0u) break;
+    bool ok = true;
+    if (threadIdx.x < 64) {
+      ok = soft_fwd_compute<T>(ring, sh, a, band, epoch);
+    } else if (band > 0) {
+      const int64_t n = a.n;
+      ok = poll_ring<T, 1>(ring, sh, ctl, n, epoch, [&](int64_t k) {
+        return a.bnd + ((int64_t)(band - 1) * n + k) * E::W;
+      });
+    }
+    if (!ok) sh.abort = 1u;
+    __syncthreads();
+  }
+  finish_launch(ctl, epoch);
+}
+
+// ---------------------------------------------------------------------------------------
+// Adjoint.
+
+template <typename T>
+__device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const SoftArgs& a, int band,
+                                                 uint32_t epoch) {
+  using E = Elem<T>;
+  using M = SoftMath<T>;
+  constexpr int W = E::W;
+  const int lane = threadIdx.x & 63;
+  const int64_t m = a.m, n = a.n;
+  const int64_t row0 = (int64_t)band * kBand;
+  const int rows = (int)(m - row0 < kBand ? m - row0 : kBand);
+  const int64_t i = row0 + lane;
+  const bool live = lane < rows;
+  const auto rc = band_rsrc<T>(a.C, row0, rows, a.ldc, n);
+  const auto rd = band_rsrc<T>(a.Din, row0, rows, a.ldd, n);
+  const auto rg = band_rsrc<T>(a.gD, row0, a.gD ? rows : 0, a.ldgd, n);
+  const auto ro = band_rsrc<T>(a.gC, row0, rows, a.ldgc, n);
+  const bool has_gd = a.gD != nullptr;
+  const T kx = (T)a.kx;
+  const bool bottom = band == a.nb - 1;  // no band below: successors below are outside
+  const bool publish = lane == 0 && band > 0;
+  const T gs = a.gscore ? *static_cast<const T*>(a.gscore) : E::zero();
+  const T NEG = -E::inf();
+  // this lane's column at step t is n - 1 - t + 63 - lane; group g covers steps 4g .. 4g+3,
+  // columns j0 - 3 .. j0 with j0 = n + 62 - lane - 4g, loaded as one 4-column vector
+  const int64_t groups = (n + 63 + 3) / 4;
+  auto first_col = [&](int64_t g) -> int64_t { return n + 62 - lane - 4 * g - 3; };
+  auto off = [&](int64_t ld, int64_t col) -> uint32_t { return (uint32_t)(((int64_t)lane * ld + col) * sizeof(T)); };
+  Vec4<T> d0 = load4_at<T>(rd, a.ldd, lane, first_col(0)), d1 = load4_at<T>(rd, a.ldd, lane, first_col(1));
+  Vec4<T> c0 = load4_at<T>(rc, a.ldc, lane, first_col(0)), c1 = load4_at<T>(rc, a.ldc, lane, first_col(1));
+  Vec4<T> g0, g1;
+  if (has_gd) {
+    g0 = load4_at<T>(rg, a.ldgd, lane, first_col(0));
+    g1 = load4_at<T>(rg, a.ldgd, lane, first_col(1));
+  }
+  T Ae = E::zero(), Ve = NEG;        // east successor: this lane's previous cell
+  T Aso = E::zero(), Vso = NEG;      // south successor of the previous step (south-east now)
+  uint64_t waited = 0;
+  for (int64_t g = 0; g < groups; ++g) {
+    const Vec4<T> dg = d0, cg = c0;
+    d0 = d1;
+    c0 = c1;
+    d1 = load4_at<T>(rd, a.ldd, lane, first_col(g + 2));
+    c1 = load4_at<T>(rc, a.ldc, lane, first_col(g + 2));
+    Vec4<T> gg;
+    if (has_gd) {
+      gg = g0;
+      g0 = g1;
+      g1 = load4_at<T>(rg, a.ldgd, lane, first_col(g + 2));
+    }
+    // the band below's row-0 (A, V) at lane 63's columns n-1-4g-q, consumer order 4g+q
+    Vec4<T> ba, bv;
+    if (bottom) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ba.v[q] = E::zero();
+        bv.v[q] = NEG;
+      }
+    } else {
+      const int64_t need = 4 * g + 4 < n ? 4 * g + 4 : n;
+      if (need > 4 * g && lds_load(&sh.avail) < (uint32_t)need) {
+        uint32_t seen;
+        if (!lds_wait_value<true, false>(&sh.avail, (uint32_t)need, &sh.abort, a.ctl, waited, seen)) return false;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t k = 4 * g + q;
+        const bool in = k < n;
+        ba.v[q] = in ? ring[(int)(k & (kRing - 1))] : E::zero();
+        bv.v[q] = in ? ring[kRing + (int)(k & (kRing - 1))] : NEG;
+      }
+    }
+    const int64_t j0 = n + 62 - lane - 4 * g;
+    Vec4<T> out;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = j0 - q;
+      const bool valid = live && j >= 0 && j < n;
+      const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
+      const T dd = dg.v[3 - q], cc = cg.v[3 - q];
+      T acc = has_gd ? gg.v[3 - q] : E::zero();
+      if (i == m - 1 && j == n - 1) acc = acc + gs;
+      acc = __builtin_fma(M::exp2_((Vso - dd) * kx), Aso, acc);
+      acc = __builtin_fma(M::exp2_((Vs - dd) * kx), As, acc);
+      acc = __builtin_fma(M::exp2_((Ve - dd) * kx), Ae, acc);
+      const T vown = dd - cc;
+      Aso = As;
+      Vso = Vs;
+      Ae = valid ? acc : E::zero();
+      Ve = valid ? vown : NEG;
+      out.v[q] = Ae;
+    }
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = j0 - q;
+        if (j >= 0 && j < n) store1<T>(ro, off(a.ldgc, j), out.v[q]);
+      }
+    }
+    if (publish) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = j0 - q;
+        if (j >= 0 && j < n) {
+          uint64_t* dst = a.bnd + ((int64_t)(band - 1) * n + j) * 2 * W;
+          const T vq = dg.v[3 - q] - cg.v[3 - q];
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            store_word(dst + w, tagged(E::word(out.v[q], w), epoch));
+            store_word(dst + W + w, tagged(E::word(vq, w), epoch));
+          }
+        }
+      }
+    }
+    if (!bottom && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * g + 4));
+  }
+  return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(128) void soft_bwd_kernel(SoftArgs a) {
+  using E = Elem<T>;
+  __shared__ T ring[2 * kRing];
+  __shared__ SoftShared sh;
+  Control* ctl = a.ctl;
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) sh.abort = 0u;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      sh.avail = 0u;
+      sh.used = 0u;
+    }
+    claim_next(ctl, &sh.item, &sh.abort);
+    // bands from the bottom up
+    const int band = a.nb - 1 - (int)sh.item;
+    if ((int)sh.item >= a.nb || sh.abort != 0u) break;
+    bool ok = true;
+    if (threadIdx.x < 64) {
+      ok = soft_bwd_compute<T>(ring, sh, a, band, epoch);
+    } else if (band < a.nb - 1) {
+      const int64_t n = a.n;
+      // consumer column k is matrix column n-1-k of the band below's first row
+      ok = poll_ring<T, 2>(ring, sh, ctl, n, epoch, [&](int64_t k) {
+        return a.bnd + ((int64_t)band * n + (n - 1 - k)) * 2 * E::W;
+      });
+    }
+    if (!ok) sh.abort = 1u;
+    __syncthreads();
+  }
+  finish_launch(ctl, epoch);
+}
+
+}  // namespace
+
+hipError_t launch_soft_forward(int dtype, const SoftArgs& a, int grid, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(soft_fwd_kernel<float>, dim3(grid), dim3(128), 0, s, a);
+  else if (dtype == 1)
+    hipLaunchKernelGGL(soft_fwd_kernel<double>, dim3(grid), dim3(128), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_soft_backward(int dtype, const SoftArgs& a, int grid, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(soft_bwd_kernel<float>, dim3(grid), dim3(128), 0, s, a);
+  else if (dtype == 1)
+    hipLaunchKernelGGL(soft_bwd_kernel<double>, dim3(grid), dim3(128), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace wf

@@ -2,7 +2,7 @@
 // place of the kernel sources: every call the driver makes fails its argument checks before
 // any launch, so these are never called.  forward_band_rows returns the library's value (one
 // 64-row sub-band per band), which the checks use.
-#include "../paper_2510_27351_amd/csrc/wf_internal.h"
+#include "../paper_2510_27351_amd/csrc/wf_soft.h"
 
 namespace wf {
 hipError_t launch_forward(int, int, const FwdArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
