@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -26,8 +27,19 @@ namespace tri {
 namespace {
 
 constexpr int kLanes = 64;                // the stage kernels run one wave per workgroup
-constexpr int kLdsBudget = 40 * 1024;     // LDS bytes a stage workgroup aims at (4 per CU)
+constexpr int kLdsBudget = 20 * 1024;     // LDS bytes a stage workgroup aims at (8 per CU)
 constexpr int kLdsMax = 64 * 1024;        // LDS bytes a stage workgroup may take at most
+
+// The LDS budget of a stage workgroup: kLdsBudget, or TRI_LDS_BUDGET (bytes, 4 KiB .. 64 KiB)
+// from the environment, read once.
+int lds_budget() {
+  static const int b = [] {
+    const char* e = std::getenv("TRI_LDS_BUDGET");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 4096 && v <= kLdsMax ? v : kLdsBudget;
+  }();
+  return b;
+}
 constexpr int kThomasThreads = 256;
 
 int elem_bytes(int dtype) { return dtype == WF_F64 ? 8 : dtype == WF_F32 ? 4 : 0; }
@@ -44,7 +56,7 @@ int pitch_of(int m) {
 // each, 64 for Stage 3), and as many as the LDS budget allows for four arrays; at least one.
 int subsystems_per_group(int m, int es, int cap) {
   const int per = 4 * pitch_of(m) * es;
-  int s = kLdsBudget / per;
+  int s = lds_budget() / per;
   if (s > cap) s = cap;
   if (s < 1) s = 1;
   return s;
@@ -306,22 +318,57 @@ __global__ __launch_bounds__(kThomasThreads) void thomas_kernel(const T* __restr
     }
     __syncthreads();
     if (t == 0) {
-      for (int q = 0; q < len; ++q) {
-        const int64_t i = i0 + q;
-        T piv, cpi, dpi;
-        if (i == 0) {
-          piv = sb[q];
-          dpi = sd[q] / piv;
-        } else {
-          piv = sb[q] - sa[q] * cprev;
-          dpi = (sd[q] - sa[q] * dprev) / piv;
+      // the chain runs through piv and the two divisions; the next rows' LDS reads are
+      // issued a group ahead so that their latency stays off it
+      constexpr int U = 8;
+      T ra[U], rb[U], rc[U], rd[U];
+      auto fetch = [&](int q0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = q0 + u < len ? q0 + u : len - 1;
+          ra[u] = sa[q];
+          rb[u] = sb[q];
+          rc[u] = sc[q];
+          rd[u] = sd[q];
         }
-        cpi = i < n - 1 ? sc[q] / piv : T(0);
-        // the stored values go to the scratch arrays through LDS (the chunk's c and d slots)
-        sc[q] = cpi;
-        sd[q] = dpi;
-        cprev = cpi;
-        dprev = dpi;
+      };
+      fetch(0);
+      for (int q0 = 0; q0 < len; q0 += U) {
+        T xa[U], xb[U], xc[U], xd[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          xa[u] = ra[u];
+          xb[u] = rb[u];
+          xc[u] = rc[u];
+          xd[u] = rd[u];
+        }
+        fetch(q0 + U < len ? q0 + U : q0);
+        T cpo[U], dpo[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t i = i0 + q0 + u;
+          T piv, dpi;
+          if (i == 0) {
+            piv = xb[u];
+            dpi = xd[u] / piv;
+          } else {
+            piv = xb[u] - xa[u] * cprev;
+            dpi = (xd[u] - xa[u] * dprev) / piv;
+          }
+          const T cpi = i < n - 1 ? xc[u] / piv : T(0);
+          cpo[u] = cpi;
+          dpo[u] = dpi;
+          cprev = cpi;
+          dprev = dpi;
+        }
+        // the stored values go to the scratch arrays through LDS (the chunk's c and d slots,
+        // already read)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (q0 + u < len) {
+            sc[q0 + u] = cpo[u];
+            sd[q0 + u] = dpo[u];
+          }
       }
     }
     __syncthreads();
@@ -342,11 +389,25 @@ __global__ __launch_bounds__(kThomasThreads) void thomas_kernel(const T* __restr
     }
     __syncthreads();
     if (t == 0) {
-      for (int q = len - 1; q >= 0; --q) {
-        const int64_t i = i0 + q;
-        const T xi = i == n - 1 ? sd[q] : sd[q] - sc[q] * xnext;
-        sa[q] = xi;
-        xnext = xi;
+      constexpr int U = 8;
+      for (int q1 = len; q1 > 0; q1 -= U) {
+        T xc[U], xd[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = q1 - 1 - u >= 0 ? q1 - 1 - u : 0;
+          xc[u] = sc[q];
+          xd[u] = sd[q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = q1 - 1 - u;
+          if (q >= 0) {
+            const int64_t i = i0 + q;
+            const T xi = i == n - 1 ? xd[u] : xd[u] - xc[u] * xnext;
+            sa[q] = xi;
+            xnext = xi;
+          }
+        }
       }
     }
     __syncthreads();
@@ -444,15 +505,53 @@ struct tri_plan {
 namespace tri {
 namespace {
 
-// Training set of the nearest-neighbour rule: for each timed system size N, the fastest
-// sub-system size m and recursion depth R on MI355X, in float64 and float32.  One hand-set
-// row (m = 32, R = 2 at N = 1e8) stands in until the timing sweep fills the table.
+// Training set of the nearest-neighbour rule: for each of the paper's 37 system sizes N (its
+// Table I), the fastest sub-system size m and recursion depth R of the device solver on one
+// MI355X, in float64 and in float32, timed by python -m paper_2510_27351_amd.tri_sweep
+// (m in {4, 8, 16, 20, 32, 40, 64, 128}, R in 0..4; best of 3 rounds of 10 solves).  A copy
+// is in tests/golden/mi355x_tri_table.txt.
 struct SizeObs {
   int64_t N;
   int32_t m64, R64, m32, R32;
 };
 const SizeObs kSizeTable[] = {
-    {100000000, 32, 2, 32, 2},
+    {100, 16, 0, 20, 0},
+    {200, 16, 0, 16, 0},
+    {400, 20, 0, 20, 0},
+    {500, 8, 1, 8, 1},
+    {800, 16, 1, 16, 1},
+    {1000, 16, 1, 16, 1},
+    {2000, 16, 1, 16, 1},
+    {4000, 20, 1, 16, 2},
+    {4500, 16, 2, 16, 2},
+    {5000, 16, 2, 16, 2},
+    {8000, 16, 2, 16, 2},
+    {10000, 16, 2, 16, 2},
+    {20000, 20, 2, 20, 2},
+    {25000, 20, 2, 16, 3},
+    {30000, 16, 3, 8, 4},
+    {40000, 16, 3, 16, 3},
+    {50000, 16, 3, 16, 3},
+    {60000, 16, 3, 16, 3},
+    {70000, 16, 3, 16, 3},
+    {75000, 16, 3, 16, 3},
+    {80000, 16, 3, 16, 3},
+    {100000, 16, 3, 16, 3},
+    {200000, 20, 3, 16, 4},
+    {400000, 16, 4, 16, 4},
+    {500000, 16, 4, 16, 4},
+    {800000, 20, 4, 16, 4},
+    {1000000, 20, 4, 16, 4},
+    {2000000, 20, 4, 20, 4},
+    {4000000, 20, 4, 20, 4},
+    {5000000, 20, 4, 20, 4},
+    {8000000, 20, 4, 32, 4},
+    {10000000, 32, 4, 32, 4},
+    {20000000, 32, 4, 32, 4},
+    {40000000, 32, 4, 32, 4},
+    {50000000, 32, 4, 32, 4},
+    {80000000, 32, 4, 32, 4},
+    {100000000, 32, 4, 32, 4},
 };
 
 // Nearest timed size (distance |log N - log N_i|, ties to the earlier row).
