@@ -135,7 +135,9 @@ __device__ __forceinline__ int sub_rows(int64_t gk, const StageArgs& g) {
 }
 
 // Stages the block's rows of the four arrays into LDS (sub-system k's row i at k*pitch + i).
-// Eight rows per lane per round, all loads of a round issued before their LDS writes.
+// Sixteen rows per lane per round, all loads of a round issued before their LDS writes: a
+// block within the LDS budget holds about 600 rows, so its loads leave in one round and
+// wait out one memory latency.
 template <typename T>
 __device__ __forceinline__ void stage_in(const StageArgs& g, const Block& bl, T* la, T* lb, T* lc, T* ld) {
   const T* __restrict__ ga = static_cast<const T*>(g.a) + bl.inst * g.n + bl.r0;
@@ -143,7 +145,7 @@ __device__ __forceinline__ void stage_in(const StageArgs& g, const Block& bl, T*
   const T* __restrict__ gc = static_cast<const T*>(g.c) + bl.inst * g.n + bl.r0;
   const T* __restrict__ gd = static_cast<const T*>(g.d) + bl.inst * g.n + bl.r0;
   const int t = threadIdx.x;
-  constexpr int U = 8;
+  constexpr int U = 16;
   for (int q0 = 0; q0 < bl.cnt; q0 += kLanes * U) {
     T va[U], vb[U], vc[U], vd[U];
 #pragma unroll

@@ -193,11 +193,29 @@ __device__ __forceinline__ T soft_cell(T c, T nw, T nn, T w, T kx, T gl) {
   return mn < E::inf() ? c + v : E::inf();
 }
 
+// 4-step groups of inputs in flight: the chain takes tens of nanoseconds per step, so the
+// loads must be issued a memory latency (1-2 us under load) ahead of their use.
+template <typename T>
+struct SoftPF {
+  static constexpr int PD = sizeof(T) == 4 ? 8 : 4;
+};
+
+// Handoff values of 4 consecutive consumer columns k0 .. k0+3 from the ring (vector NV-th
+// plane), or 'fill' past the last column.
+template <typename T>
+__device__ __forceinline__ Vec4<T> ring4(const T* ring, int64_t k0, int64_t n, T fill) {
+  Vec4<T> v;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v.v[q] = k0 + q < n ? ring[(int)((k0 + q) & (kRing - 1))] : fill;
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const SoftArgs& a, int band,
                                                  uint32_t epoch) {
   using E = Elem<T>;
   constexpr int W = E::W;
+  constexpr int PD = SoftPF<T>::PD;
   const int lane = threadIdx.x & 63;
   const int64_t m = a.m, n = a.n;
   const int64_t row0 = (int64_t)band * kBand;
@@ -214,67 +232,91 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const 
   auto off_c = [&](int64_t g) -> uint32_t { return (uint32_t)(((int64_t)lane * a.ldc + 4 * g - lane) * sizeof(T)); };
   auto off_d = [&](int64_t col) -> uint32_t { return (uint32_t)(((int64_t)lane * a.ldd + col) * sizeof(T)); };
   T X = E::inf(), NW = (first && lane == 0) ? E::zero() : E::inf();
-  Vec4<T> c0 = load4<T>(rc, off_c(0)), c1 = load4<T>(rc, off_c(1));
+  Vec4<T> cb[PD];
+#pragma unroll
+  for (int k = 0; k < PD; ++k) cb[k] = load4<T>(rc, off_c(k));
   uint64_t waited = 0;
-  for (int64_t g = 0; g < groups; ++g) {
-    const Vec4<T> cg = c0;
-    c0 = c1;
-    c1 = load4<T>(rc, off_c(g + 2));
-    // the top row's columns 4g .. 4g+3 (lane 0's)
-    Vec4<T> top;
-    if (first) {
+  // top-row columns known to be in the ring (wave-uniform); the first band's top row is
+  // virtual (+inf) and needs no ring
+  uint32_t have = first ? 0xffffffffu : 0u;
+  auto avail_for = [&](int64_t g) -> bool {  // waits until group g's top columns are in the ring
+    const int64_t need = 4 * g + 4 < n ? 4 * g + 4 : n;
+    if (need <= (int64_t)have) return true;
+    have = lds_load(&sh.avail);
+    if (need <= (int64_t)have) return true;
+    uint32_t seen;
+    if (!lds_wait_value<true, false>(&sh.avail, (uint32_t)need, &sh.abort, a.ctl, waited, seen)) return false;
+    have = seen;
+    return true;
+  };
+  Vec4<T> top;
+  if (!first) {
+    if (!avail_for(0)) return false;
+    top = ring4<T>(ring, 0, n, E::inf());
+  } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) top.v[q] = E::inf();
-    } else {
-      const int64_t need = 4 * g + 4 < n ? 4 * g + 4 : n;
-      if (need > 4 * g && lds_load(&sh.avail) < (uint32_t)need) {
-        uint32_t seen;
-        if (!lds_wait_value<true, false>(&sh.avail, (uint32_t)need, &sh.abort, a.ctl, waited, seen)) return false;
-      }
+    for (int q = 0; q < 4; ++q) top.v[q] = E::inf();
+  }
+  for (int64_t g0 = 0; g0 < groups; g0 += PD) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t col = 4 * g + q;
-        top.v[q] = col < n ? ring[(int)(col & (kRing - 1))] : E::inf();
-      }
-    }
-    Vec4<T> out;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T N = E::shr1(X, top.v[q]);
-      X = soft_cell<T>(cg.v[q], NW, N, X, kx, gl);
-      NW = N;
-      out.v[q] = X;
-    }
-    // columns 4g - lane .. 4g - lane + 3 of row i
-    const int64_t col0 = 4 * g - lane;
-    if (live) {
-      if (col0 >= 0 && col0 + 3 < n) {
-        if constexpr (sizeof(T) == 4) {
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, out),
-                                                 rd, off_d(col0), 0, 0);
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) store1<T>(rd, off_d(col0 + q), out.v[q]);
+    for (int k = 0; k < PD; ++k) {
+      const int64_t g = g0 + k;
+      if (g < groups) {
+        const Vec4<T> cg = cb[k];
+        cb[k] = load4<T>(rc, off_c(g + PD));
+        // the next group's top values, read now if they are in the ring (else after this
+        // group, once they are)
+        Vec4<T> tnext = top;
+        bool tn_ready = first;
+        if (!first && g + 1 < groups && 4 * g + 8 <= (int64_t)have) {
+          tnext = ring4<T>(ring, 4 * g + 4, n, E::inf());
+          tn_ready = true;
         }
-      } else {
+        Vec4<T> out;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (col0 + q >= 0 && col0 + q < n) store1<T>(rd, off_d(col0 + q), out.v[q]);
-      }
-      if (i == m - 1 && col0 <= n - 1 && n - 1 <= col0 + 3) static_cast<T*>(a.score)[0] = out.v[n - 1 - col0];
-    }
-    if (publish) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t col = col0 + q;
-        if (col >= 0 && col < n) {
-#pragma unroll
-          for (int w = 0; w < W; ++w)
-            store_word(a.bnd + ((int64_t)band * n + col) * W + w, tagged(E::word(out.v[q], w), epoch));
+        for (int q = 0; q < 4; ++q) {
+          const T N = E::shr1(X, top.v[q]);
+          X = soft_cell<T>(cg.v[q], NW, N, X, kx, gl);
+          NW = N;
+          out.v[q] = X;
         }
+        // columns 4g - lane .. 4g - lane + 3 of row i
+        const int64_t col0 = 4 * g - lane;
+        if (live) {
+          if (col0 >= 0 && col0 + 3 < n) {
+            if constexpr (sizeof(T) == 4) {
+              __builtin_amdgcn_raw_buffer_store_b128(
+                  __builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, out), rd, off_d(col0), 0, 0);
+            } else {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) store1<T>(rd, off_d(col0 + q), out.v[q]);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (col0 + q >= 0 && col0 + q < n) store1<T>(rd, off_d(col0 + q), out.v[q]);
+          }
+          if (i == m - 1 && col0 <= n - 1 && n - 1 <= col0 + 3) static_cast<T*>(a.score)[0] = out.v[n - 1 - col0];
+        }
+        if (publish) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t col = col0 + q;
+            if (col >= 0 && col < n) {
+#pragma unroll
+              for (int w = 0; w < W; ++w)
+                store_word(a.bnd + ((int64_t)band * n + col) * W + w, tagged(E::word(out.v[q], w), epoch));
+            }
+          }
+        }
+        if (!tn_ready && g + 1 < groups) {
+          if (!avail_for(g + 1)) return false;
+          tnext = ring4<T>(ring, 4 * g + 4, n, E::inf());
+        }
+        top = tnext;
       }
     }
-    if (!first && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * g + 4));
+    if (!first && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * (g0 + PD) < n ? 4 * (g0 + PD) : n));
   }
   return true;
 }
@@ -319,6 +361,7 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const 
   using E = Elem<T>;
   using M = SoftMath<T>;
   constexpr int W = E::W;
+  constexpr int PD = SoftPF<T>::PD;
   const int lane = threadIdx.x & 63;
   const int64_t m = a.m, n = a.n;
   const int64_t row0 = (int64_t)band * kBand;
@@ -340,93 +383,129 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const 
   const int64_t groups = (n + 63 + 3) / 4;
   auto first_col = [&](int64_t g) -> int64_t { return n + 62 - lane - 4 * g - 3; };
   auto off = [&](int64_t ld, int64_t col) -> uint32_t { return (uint32_t)(((int64_t)lane * ld + col) * sizeof(T)); };
-  Vec4<T> d0 = load4_at<T>(rd, a.ldd, lane, first_col(0)), d1 = load4_at<T>(rd, a.ldd, lane, first_col(1));
-  Vec4<T> c0 = load4_at<T>(rc, a.ldc, lane, first_col(0)), c1 = load4_at<T>(rc, a.ldc, lane, first_col(1));
-  Vec4<T> g0, g1;
-  if (has_gd) {
-    g0 = load4_at<T>(rg, a.ldgd, lane, first_col(0));
-    g1 = load4_at<T>(rg, a.ldgd, lane, first_col(1));
+  Vec4<T> db[PD], cb[PD], gb[PD];
+#pragma unroll
+  for (int k = 0; k < PD; ++k) {
+    db[k] = load4_at<T>(rd, a.ldd, lane, first_col(k));
+    cb[k] = load4_at<T>(rc, a.ldc, lane, first_col(k));
+    if (has_gd) gb[k] = load4_at<T>(rg, a.ldgd, lane, first_col(k));
   }
   T Ae = E::zero(), Ve = NEG;        // east successor: this lane's previous cell
   T Aso = E::zero(), Vso = NEG;      // south successor of the previous step (south-east now)
   uint64_t waited = 0;
-  for (int64_t g = 0; g < groups; ++g) {
-    const Vec4<T> dg = d0, cg = c0;
-    d0 = d1;
-    c0 = c1;
-    d1 = load4_at<T>(rd, a.ldd, lane, first_col(g + 2));
-    c1 = load4_at<T>(rc, a.ldc, lane, first_col(g + 2));
-    Vec4<T> gg;
-    if (has_gd) {
-      gg = g0;
-      g0 = g1;
-      g1 = load4_at<T>(rg, a.ldgd, lane, first_col(g + 2));
-    }
-    // the band below's row-0 (A, V) at lane 63's columns n-1-4g-q, consumer order 4g+q
-    Vec4<T> ba, bv;
-    if (bottom) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ba.v[q] = E::zero();
-        bv.v[q] = NEG;
-      }
-    } else {
-      const int64_t need = 4 * g + 4 < n ? 4 * g + 4 : n;
-      if (need > 4 * g && lds_load(&sh.avail) < (uint32_t)need) {
-        uint32_t seen;
-        if (!lds_wait_value<true, false>(&sh.avail, (uint32_t)need, &sh.abort, a.ctl, waited, seen)) return false;
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t k = 4 * g + q;
-        const bool in = k < n;
-        ba.v[q] = in ? ring[(int)(k & (kRing - 1))] : E::zero();
-        bv.v[q] = in ? ring[kRing + (int)(k & (kRing - 1))] : NEG;
-      }
-    }
-    const int64_t j0 = n + 62 - lane - 4 * g;
-    Vec4<T> out;
+  // columns of the band below's first row known to be in the ring (wave-uniform)
+  uint32_t have = bottom ? 0xffffffffu : 0u;
+  auto avail_for = [&](int64_t g) -> bool {
+    const int64_t need = 4 * g + 4 < n ? 4 * g + 4 : n;
+    if (need <= (int64_t)have) return true;
+    have = lds_load(&sh.avail);
+    if (need <= (int64_t)have) return true;
+    uint32_t seen;
+    if (!lds_wait_value<true, false>(&sh.avail, (uint32_t)need, &sh.abort, a.ctl, waited, seen)) return false;
+    have = seen;
+    return true;
+  };
+  // the band below's row-0 (A, V) at lane 63's columns n-1-4g-q, consumer order 4g+q
+  Vec4<T> ba, bv;
+  auto read_bottom = [&](int64_t g, Vec4<T>& va, Vec4<T>& vv) {
+    va = ring4<T>(ring, 4 * g, n, E::zero());
+    vv = ring4<T>(ring + kRing, 4 * g, n, NEG);
+  };
+  if (bottom) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t j = j0 - q;
-      const bool valid = live && j >= 0 && j < n;
-      const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
-      const T dd = dg.v[3 - q], cc = cg.v[3 - q];
-      T acc = has_gd ? gg.v[3 - q] : E::zero();
-      if (i == m - 1 && j == n - 1) acc = acc + gs;
-      acc = __builtin_fma(M::exp2_((Vso - dd) * kx), Aso, acc);
-      acc = __builtin_fma(M::exp2_((Vs - dd) * kx), As, acc);
-      acc = __builtin_fma(M::exp2_((Ve - dd) * kx), Ae, acc);
-      const T vown = dd - cc;
-      Aso = As;
-      Vso = Vs;
-      Ae = valid ? acc : E::zero();
-      Ve = valid ? vown : NEG;
-      out.v[q] = Ae;
+      ba.v[q] = E::zero();
+      bv.v[q] = NEG;
     }
-    if (live) {
+  } else {
+    if (!avail_for(0)) return false;
+    read_bottom(0, ba, bv);
+  }
+  for (int64_t g0 = 0; g0 < groups; g0 += PD) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t j = j0 - q;
-        if (j >= 0 && j < n) store1<T>(ro, off(a.ldgc, j), out.v[q]);
-      }
-    }
-    if (publish) {
+    for (int k = 0; k < PD; ++k) {
+      const int64_t g = g0 + k;
+      if (g < groups) {
+        const Vec4<T> dg = db[k], cg = cb[k];
+        db[k] = load4_at<T>(rd, a.ldd, lane, first_col(g + PD));
+        cb[k] = load4_at<T>(rc, a.ldc, lane, first_col(g + PD));
+        Vec4<T> gg;
+        if (has_gd) {
+          gg = gb[k];
+          gb[k] = load4_at<T>(rg, a.ldgd, lane, first_col(g + PD));
+        }
+        Vec4<T> na = ba, nv = bv;
+        bool n_ready = bottom;
+        if (!bottom && g + 1 < groups && 4 * g + 8 <= (int64_t)have) {
+          read_bottom(g + 1, na, nv);
+          n_ready = true;
+        }
+        const int64_t j0 = n + 62 - lane - 4 * g;
+        Vec4<T> out;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t j = j0 - q;
-        if (j >= 0 && j < n) {
-          uint64_t* dst = a.bnd + ((int64_t)(band - 1) * n + j) * 2 * W;
-          const T vq = dg.v[3 - q] - cg.v[3 - q];
+        for (int q = 0; q < 4; ++q) {
+          const int64_t j = j0 - q;
+          const bool valid = live && j >= 0 && j < n;
+          const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
+          const T dd = dg.v[3 - q], cc = cg.v[3 - q];
+          T acc = has_gd ? gg.v[3 - q] : E::zero();
+          if (i == m - 1 && j == n - 1) acc = acc + gs;
+          acc = __builtin_fma(M::exp2_((Vso - dd) * kx), Aso, acc);
+          acc = __builtin_fma(M::exp2_((Vs - dd) * kx), As, acc);
+          acc = __builtin_fma(M::exp2_((Ve - dd) * kx), Ae, acc);
+          const T vown = dd - cc;
+          Aso = As;
+          Vso = Vs;
+          Ae = valid ? acc : E::zero();
+          Ve = valid ? vown : NEG;
+          out.v[q] = Ae;
+        }
+        if (live) {
+          // the group's columns are j0-3 .. j0, out.v[q] at column j0 - q
+          bool whole = false;
+          if constexpr (sizeof(T) == 4) {
+            if (j0 - 3 >= 0 && j0 < n) {
+              Vec4<T> asc;
 #pragma unroll
-          for (int w = 0; w < W; ++w) {
-            store_word(dst + w, tagged(E::word(out.v[q], w), epoch));
-            store_word(dst + W + w, tagged(E::word(vq, w), epoch));
+              for (int q = 0; q < 4; ++q) asc.v[q] = out.v[3 - q];
+              __builtin_amdgcn_raw_buffer_store_b128(
+                  __builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, asc), ro, off(a.ldgc, j0 - 3), 0,
+                  0);
+              whole = true;
+            }
+          }
+          if (!whole) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int64_t j = j0 - q;
+              if (j >= 0 && j < n) store1<T>(ro, off(a.ldgc, j), out.v[q]);
+            }
           }
         }
+        if (publish) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t j = j0 - q;
+            if (j >= 0 && j < n) {
+              uint64_t* dst = a.bnd + ((int64_t)(band - 1) * n + j) * 2 * W;
+              const T vq = dg.v[3 - q] - cg.v[3 - q];
+#pragma unroll
+              for (int w = 0; w < W; ++w) {
+                store_word(dst + w, tagged(E::word(out.v[q], w), epoch));
+                store_word(dst + W + w, tagged(E::word(vq, w), epoch));
+              }
+            }
+          }
+        }
+        if (!n_ready && g + 1 < groups) {
+          if (!avail_for(g + 1)) return false;
+          read_bottom(g + 1, na, nv);
+        }
+        ba = na;
+        bv = nv;
       }
     }
-    if (!bottom && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * g + 4));
+    if (!bottom && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * (g0 + PD) < n ? 4 * (g0 + PD) : n));
   }
   return true;
 }
