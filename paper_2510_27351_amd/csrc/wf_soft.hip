@@ -70,12 +70,19 @@ __device__ __forceinline__ Vec4<T> load4(__amdgpu_buffer_rsrc_t r, uint32_t off)
 template <typename T>
 __device__ __forceinline__ Vec4<T> load4_at(__amdgpu_buffer_rsrc_t r, int64_t ld, int lane, int64_t col) {
   const int64_t e = (int64_t)lane * ld + col;
-  if (e >= 0) return load4<T>(r, (uint32_t)(e * (int64_t)sizeof(T)));
-  const Vec4<T> v = load4<T>(r, 0u);
-  const int sh = (int)-e;  // 1 .. 3
+  const Vec4<T> v = load4<T>(r, e >= 0 ? (uint32_t)(e * (int64_t)sizeof(T)) : 0u);
+  if (!__any(e < 0)) return v;  // wave-uniform: the shift is needed in the last groups only
+  const int sh = e < 0 ? (int)-e : 0;
   Vec4<T> o = v;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) o.v[q] = q >= sh ? v.v[q - sh] : v.v[0];
+  for (int q = 0; q < 4; ++q) {
+    T x = v.v[0];
+#pragma unroll
+    for (int p = 0; p < q; ++p)
+      if (q - sh == p) x = v.v[p];
+    if (sh == 0) x = v.v[q];
+    o.v[q] = x;
+  }
   return o;
 }
 
@@ -183,14 +190,18 @@ __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl,
 // ---------------------------------------------------------------------------------------
 // Forward.
 
+// One cell in the scaled domain y = D log2(e) / gamma: the soft minimum of the scaled
+// neighbours is ymn - log2(sum_k 2^(ymn - y_k)) with ymn their minimum, and the cell's value
+// adds the scaled input yc.  Three inputs of +inf (the padding lanes before column 0) give
+// +inf, not NaN.
 template <typename T>
-__device__ __forceinline__ T soft_cell(T c, T nw, T nn, T w, T kx, T gl) {
+__device__ __forceinline__ T soft_cell(T yc, T ynw, T yn, T yw) {
   using M = SoftMath<T>;
   using E = Elem<T>;
-  const T mn = E::min3(nw, nn, w);
-  const T s = M::exp2_((mn - nw) * kx) + M::exp2_((mn - nn) * kx) + M::exp2_((mn - w) * kx);
-  const T v = mn - gl * M::log2_(s);
-  return mn < E::inf() ? c + v : E::inf();
+  const T ymn = E::min3(ynw, yn, yw);
+  const T s = M::exp2_(ymn - ynw) + M::exp2_(ymn - yn) + M::exp2_(ymn - yw);
+  const T y = yc + (ymn - M::log2_(s));
+  return ymn < E::inf() ? y : E::inf();
 }
 
 // 4-step groups of inputs in flight: the chain takes tens of nanoseconds per step, so the
@@ -224,14 +235,17 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const 
   const bool live = lane < rows;
   const auto rc = band_rsrc<T>(a.C, row0, rows, a.ldc, n);
   const auto rd = band_rsrc<T>(a.D, row0, rows, a.ldd, n);
+  // the chain runs in the scaled domain y = D * kx; stored and published values are D
   const T kx = (T)a.kx, gl = (T)a.gl;
   const bool first = band == 0;
   const bool publish = lane == 63 && band < a.nb - 1;
-  // this lane's column at step t is t - lane; group g covers steps 4g .. 4g+3
+  // this lane's column at step t is t - lane; group g covers steps 4g .. 4g+3.  Groups
+  // [g_lo, g_hi) have every lane's four columns inside the matrix (a full band only).
   const int64_t groups = (n + 63 + 3) / 4;
+  const int64_t g_lo = rows == kBand ? 16 : groups, g_hi = rows == kBand ? n / 4 : 0;
   auto off_c = [&](int64_t g) -> uint32_t { return (uint32_t)(((int64_t)lane * a.ldc + 4 * g - lane) * sizeof(T)); };
   auto off_d = [&](int64_t col) -> uint32_t { return (uint32_t)(((int64_t)lane * a.ldd + col) * sizeof(T)); };
-  T X = E::inf(), NW = (first && lane == 0) ? E::zero() : E::inf();
+  T Y = E::inf(), NW = (first && lane == 0) ? E::zero() : E::inf();
   Vec4<T> cb[PD];
 #pragma unroll
   for (int k = 0; k < PD; ++k) cb[k] = load4<T>(rc, off_c(k));
@@ -249,6 +263,7 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const 
     have = seen;
     return true;
   };
+  // the band above's published values are scaled (y); +inf past the matrix
   Vec4<T> top;
   if (!first) {
     if (!avail_for(0)) return false;
@@ -264,48 +279,55 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const 
       if (g < groups) {
         const Vec4<T> cg = cb[k];
         cb[k] = load4<T>(rc, off_c(g + PD));
-        // the next group's top values, read now if they are in the ring (else after this
-        // group, once they are)
         Vec4<T> tnext = top;
         bool tn_ready = first;
         if (!first && g + 1 < groups && 4 * g + 8 <= (int64_t)have) {
           tnext = ring4<T>(ring, 4 * g + 4, n, E::inf());
           tn_ready = true;
         }
-        Vec4<T> out;
+        Vec4<T> ys, out;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const T N = E::shr1(X, top.v[q]);
-          X = soft_cell<T>(cg.v[q], NW, N, X, kx, gl);
+          const T N = E::shr1(Y, top.v[q]);
+          Y = soft_cell<T>(cg.v[q] * kx, NW, N, Y);
           NW = N;
-          out.v[q] = X;
+          ys.v[q] = Y;
+          out.v[q] = Y * gl;
         }
-        // columns 4g - lane .. 4g - lane + 3 of row i
-        const int64_t col0 = 4 * g - lane;
-        if (live) {
-          if (col0 >= 0 && col0 + 3 < n) {
-            if constexpr (sizeof(T) == 4) {
-              __builtin_amdgcn_raw_buffer_store_b128(
-                  __builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, out), rd, off_d(col0), 0, 0);
-            } else {
-#pragma unroll
-              for (int q = 0; q < 4; ++q) store1<T>(rd, off_d(col0 + q), out.v[q]);
-            }
+        const int64_t col0 = 4 * g - lane;  // columns col0 .. col0+3 of row i
+        if (g >= g_lo && g < g_hi) {
+          // interior group: every cell of every lane lies in the matrix (the last cell, which
+          // holds the score, is never in one)
+          if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b128(
+                __builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, out), rd, off_d(col0), 0, 0);
           } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) store1<T>(rd, off_d(col0 + q), out.v[q]);
+          }
+          if (publish) {
+            uint64_t* dst = a.bnd + ((int64_t)band * n + col0) * W;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int w = 0; w < W; ++w) store_word(dst + q * W + w, tagged(E::word(ys.v[q], w), epoch));
+          }
+        } else {
+          if (live) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               if (col0 + q >= 0 && col0 + q < n) store1<T>(rd, off_d(col0 + q), out.v[q]);
+            if (i == m - 1 && col0 <= n - 1 && n - 1 <= col0 + 3) static_cast<T*>(a.score)[0] = out.v[n - 1 - col0];
           }
-          if (i == m - 1 && col0 <= n - 1 && n - 1 <= col0 + 3) static_cast<T*>(a.score)[0] = out.v[n - 1 - col0];
-        }
-        if (publish) {
+          if (publish) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int64_t col = col0 + q;
-            if (col >= 0 && col < n) {
+            for (int q = 0; q < 4; ++q) {
+              const int64_t col = col0 + q;
+              if (col >= 0 && col < n) {
 #pragma unroll
-              for (int w = 0; w < W; ++w)
-                store_word(a.bnd + ((int64_t)band * n + col) * W + w, tagged(E::word(out.v[q], w), epoch));
+                for (int w = 0; w < W; ++w)
+                  store_word(a.bnd + ((int64_t)band * n + col) * W + w, tagged(E::word(ys.v[q], w), epoch));
+              }
             }
           }
         }
@@ -381,6 +403,10 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const 
   // this lane's column at step t is n - 1 - t + 63 - lane; group g covers steps 4g .. 4g+3,
   // columns j0 - 3 .. j0 with j0 = n + 62 - lane - 4g, loaded as one 4-column vector
   const int64_t groups = (n + 63 + 3) / 4;
+  // groups [g_lo, g_hi) have every lane's four columns inside the matrix (a full band only):
+  // lane 0's highest column n+62-4g <= n-1 needs g >= 16, lane 63's lowest n-4-4g >= 0 needs
+  // g <= (n-4)/4
+  const int64_t g_lo = rows == kBand ? 16 : groups, g_hi = rows == kBand && n >= 4 ? (n - 4) / 4 + 1 : 0;
   auto first_col = [&](int64_t g) -> int64_t { return n + 62 - lane - 4 * g - 3; };
   auto off = [&](int64_t ld, int64_t col) -> uint32_t { return (uint32_t)(((int64_t)lane * ld + col) * sizeof(T)); };
   Vec4<T> db[PD], cb[PD], gb[PD];
@@ -441,30 +467,50 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const 
           n_ready = true;
         }
         const int64_t j0 = n + 62 - lane - 4 * g;
+        // interior group (full band, every lane's columns j0-3 .. j0 inside the matrix, the
+        // last cell not among them): no validity selects, one vector store
+        const bool interior = g >= g_lo && g < g_hi;
         Vec4<T> out;
+        if (interior) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t j = j0 - q;
-          const bool valid = live && j >= 0 && j < n;
-          const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
-          const T dd = dg.v[3 - q], cc = cg.v[3 - q];
-          T acc = has_gd ? gg.v[3 - q] : E::zero();
-          if (i == m - 1 && j == n - 1) acc = acc + gs;
-          acc = __builtin_fma(M::exp2_((Vso - dd) * kx), Aso, acc);
-          acc = __builtin_fma(M::exp2_((Vs - dd) * kx), As, acc);
-          acc = __builtin_fma(M::exp2_((Ve - dd) * kx), Ae, acc);
-          const T vown = dd - cc;
-          Aso = As;
-          Vso = Vs;
-          Ae = valid ? acc : E::zero();
-          Ve = valid ? vown : NEG;
-          out.v[q] = Ae;
+          for (int q = 0; q < 4; ++q) {
+            const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
+            const T dd = dg.v[3 - q], cc = cg.v[3 - q];
+            T acc = has_gd ? gg.v[3 - q] : E::zero();
+            acc = __builtin_fma(M::exp2_((Vso - dd) * kx), Aso, acc);
+            acc = __builtin_fma(M::exp2_((Vs - dd) * kx), As, acc);
+            acc = __builtin_fma(M::exp2_((Ve - dd) * kx), Ae, acc);
+            Aso = As;
+            Vso = Vs;
+            Ae = acc;
+            Ve = dd - cc;
+            out.v[q] = acc;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t j = j0 - q;
+            const bool valid = live && j >= 0 && j < n;
+            const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
+            const T dd = dg.v[3 - q], cc = cg.v[3 - q];
+            T acc = has_gd ? gg.v[3 - q] : E::zero();
+            if (i == m - 1 && j == n - 1) acc = acc + gs;
+            acc = __builtin_fma(M::exp2_((Vso - dd) * kx), Aso, acc);
+            acc = __builtin_fma(M::exp2_((Vs - dd) * kx), As, acc);
+            acc = __builtin_fma(M::exp2_((Ve - dd) * kx), Ae, acc);
+            const T vown = dd - cc;
+            Aso = As;
+            Vso = Vs;
+            Ae = valid ? acc : E::zero();
+            Ve = valid ? vown : NEG;
+            out.v[q] = Ae;
+          }
         }
         if (live) {
           // the group's columns are j0-3 .. j0, out.v[q] at column j0 - q
           bool whole = false;
           if constexpr (sizeof(T) == 4) {
-            if (j0 - 3 >= 0 && j0 < n) {
+            if (interior || (j0 - 3 >= 0 && j0 < n)) {
               Vec4<T> asc;
 #pragma unroll
               for (int q = 0; q < 4; ++q) asc.v[q] = out.v[3 - q];

@@ -3,8 +3,16 @@
 The device evaluates its exponentials and logarithms with its own base-2 functions, so the
 comparison with the float64 oracle (oracle/softmin.c, pinned by path enumeration) is within
 rounding, not bitwise.  Bars:
-  - float64: every element within 1e-10 relative of the oracle (a few units in the last
-    place per cell, accumulated along paths of at most m+n-1 cells);
+  - float64: every table element within 1e-10 relative of the oracle (a few units in the
+    last place per cell, accumulated along paths of at most m+n-1 cells).  The gradient
+    multiplies the weights along paths, and their exponents telescope, so its relative error
+    is the absolute rounding drift of the forward table over a path divided by gamma; each
+    side's drift is a sum of L = m+n-1 roundings of at most a few u max|D| (u = 2^-53), which
+    the probabilistic rounding-error bound of Higham and Mary (SISC 2019) holds to
+    lambda sqrt(L) u max|D| with overwhelming probability.  Bar: max(1e-10,
+    12 sqrt(L) u max|D*| / gamma) (two sides, lambda times rounding count 6).  At 70000 x 6
+    this is what separates two correct evaluations: the oracle's own adjoint differs by
+    5e-10 from that of the exactly rounded table (long double evaluation);
   - float32: error <= 1e-4 against the float64 oracle (the library's float32 bar), stated
     per result.  Each soft minimum lies up to gamma log 3 below the plain minimum, so the
     table crosses zero even for positive inputs and a relative error is ill-posed at the
@@ -34,6 +42,10 @@ DEV = "cuda:0"
 def rel(got, want):
     got = got.astype(np.float64)
     return float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-300)))
+
+
+def f64_grad_bar(m, n, Dmax, gamma):
+    return max(1e-10, 12 * np.sqrt(m + n - 1) * 2.0 ** -53 * Dmax / gamma)
 
 
 def grad_err(got, want, cut=1e-3):
@@ -83,8 +95,9 @@ def test_backward_f64(shape, gamma, oracle_mod):
     Dn = oracle_mod.soft_forward(C.numpy(), gamma)
     want = oracle_mod.soft_backward(C.numpy(), Dn, gamma, gD=gD.numpy(), gscore=0.75)
     err = float(np.max(np.abs(g.cpu().numpy() - want)) / max(1e-300, np.max(np.abs(want))))
-    print(f"soft adjoint f64 {shape} gamma={gamma}: max err / max|g| {err:.2e}")
-    assert err <= 1e-10
+    bar = f64_grad_bar(*shape, float(np.max(np.abs(Dn))), gamma)
+    print(f"soft adjoint f64 {shape} gamma={gamma}: max err / max|g| {err:.2e} (bar {bar:.2e})")
+    assert err <= bar
 
 
 @pytest.mark.parametrize("shape", SHAPES[2:])
@@ -137,8 +150,9 @@ def test_more_bands_than_workgroups(oracle_mod):
     D32, _ = wf.soft_forward(Cd.float(), gamma)
     fel, fnw = grad_err(D32.cpu().numpy(), oracle_mod.soft_forward(C.float().numpy().astype(np.float64), gamma),
                         cut=1e-2)
-    print(f"70000x6: f64 adjoint {err:.2e}; f32 forward normwise {fnw:.2e} elementwise {fel:.2e}")
-    assert err <= 1e-10 and fnw <= 1e-4 and fel <= 1e-4
+    bar = f64_grad_bar(m, n, float(np.max(np.abs(Dn))), gamma)
+    print(f"70000x6: f64 adjoint {err:.2e} (bar {bar:.2e}); f32 forward normwise {fnw:.2e} elementwise {fel:.2e}")
+    assert err <= bar and fnw <= 1e-4 and fel <= 1e-4
 
 
 def test_finite_differences_f64():
