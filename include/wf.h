@@ -24,11 +24,13 @@
  *   - Return value: WF_OK or an error code.  Arguments are validated before any device work;
  *     on an argument error nothing is enqueued.  A device-side failure (a bounded wait that
  *     expired) is reported by wf_last_async_error().
- *   - The library keeps one internal workspace per device (handoff words, counters), created
- *     on the first call on that device and grown when a larger shape arrives (growing
- *     allocates and synchronizes the device).  Calls that share a device must be ordered
- *     (one stream, or streams joined by events): two overlapping calls on one device race on
- *     that workspace.
+ *   - The library keeps one internal workspace per (device, stream) pair (control block,
+ *     handoff words, selections), created on the first call on that stream and grown when a
+ *     larger shape arrives (growing allocates and synchronizes the device).  Calls on one
+ *     stream are ordered by it; calls on different streams of a device use different
+ *     workspaces and may overlap.  A workspace lives until the process ends, keyed by the
+ *     stream handle, so a program that creates streams without bound should reuse them.
+ *     Plans own their control block; wf_forward_noalloc uses one array per device instead.
  *   - Leading dimensions are limited to (2^31 / 128 - 16) bytes (about 4.2 million float
  *     columns): larger values return WF_E_UNSUPPORTED.
  *   - Element types: WF_F32 (float, one IEEE add per cell, min exact), WF_F64 (double),
@@ -124,11 +126,10 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
  * The two halves of wf_backward, for callers that time or schedule them separately
  * (wf_backward is exactly wf_select followed by wf_reverse on the same stream).
  * wf_select recomputes the predecessor selections of an m x n forward sweep (arguments as
- * for wf_backward) into the calling device's workspace; wf_reverse runs the reverse sweep
- * from them and writes g_C.  wf_reverse returns WF_E_ARG unless the last wf_select enqueued
- * on this device was for the same dtype, m and n; the workspace holds one set of
- * selections per device, so select/reverse pairs on different streams of one device must
- * not interleave.
+ * for wf_backward) into the workspace of (current device, 'stream'); wf_reverse runs the
+ * reverse sweep from them and writes g_C.  wf_reverse must be given the stream of its
+ * wf_select: it returns WF_E_ARG unless the last wf_select enqueued on that stream of this
+ * device was for the same dtype, m and n (a workspace holds one set of selections).
  */
 int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt,
               int32_t ckpt_k, const void* D, int64_t ldd, void* stream);
@@ -166,8 +167,8 @@ int wf_reverse(int dtype, int64_t m, int64_t n, const void* g_score, const void*
  *   C       [in]  device buffer of wf_plan_elems elements holding every instance.
  *   D       [out] same layout as C, every instance's table; NULL = scores only.
  *   scores  [out] 'batch' elements, D_i[m_i-1][n_i-1].
- *   The plan's device of creation must be current.  Calls on one plan must be ordered; a
- *   plan shares the device workspace's control block with the other entry points.
+ *   The plan's device of creation must be current.  Calls on one plan must be ordered (its
+ *   control block and buffers are its own); different plans may run on different streams.
  * wf_plan_destroy  synchronizes the device and frees the plan (NULL is ignored).
  */
 typedef struct wf_plan wf_plan;
@@ -251,15 +252,18 @@ int wf_trace_enable(int64_t max_bands);
 int64_t wf_trace_fetch(uint64_t* host, int64_t max_bands);
 
 /*
- * Synchronizes 'stream', then reports and clears the device-side error state of the
- * current device's workspace: WF_OK, or WF_E_TIMEOUT if a bounded wait expired in any call
- * since the last check (the outputs of such a call are undefined).
+ * Synchronizes 'stream', then reports and clears the device-side error state of every
+ * control block of the current device (the workspaces of all its streams, its plans and the
+ * allocation-free array): WF_OK, or WF_E_TIMEOUT if a bounded wait expired in any call since
+ * the last check (the outputs of such a call are undefined).  Work still running on other
+ * streams is not waited for: synchronize them first to have their errors included.
  */
 int wf_last_async_error(void* stream);
 
 /*
- * Fault injection, for tests of the failure path only.  Sets the mode of the current
- * device's workspace for every later sweep on that device until it is set back to 0:
+ * Fault injection, for tests of the failure path only.  Sets the mode of every control block
+ * of the current device (all streams, plans, the allocation-free array, and those created
+ * later) for every later sweep on that device until it is set back to 0:
  *   0  no fault (the default);
  *   1  in wf_forward (and the ragged batch), band 0 publishes no boundary row: the band below
  *      waits until its bounded wait (2 s) expires, raises WF_E_TIMEOUT and every workgroup of

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -15,6 +16,7 @@
 #include <vector>
 
 #include "../../include/wf.h"
+#include "wf_host.h"
 #include "wf_internal.h"
 #include "wf_soft.h"
 
@@ -22,28 +24,51 @@ namespace wf {
 namespace {
 
 std::mutex g_mu;
-std::vector<DeviceWs> g_ws;
+// One workspace per (device, stream): sweeps on different streams of a device never share a
+// control block, handoff words or selections.  Map nodes keep their addresses.
+std::map<std::pair<int, hipStream_t>, DeviceWs> g_ws;
+std::vector<uint32_t> g_fault;                   // per device: injected fault mode (tests)
+std::vector<std::pair<int, Control*>> g_plan_ctl;  // control blocks owned by plans
 int g_tile_override = 0;
 // optional per-band trace buffer (one, for the device that enabled it)
 uint64_t* g_trace = nullptr;
 int64_t g_trace_bands = 0;
 int g_trace_dev = -1;
 
+uint32_t fault_of(int dev) { return dev < (int)g_fault.size() ? g_fault[dev] : 0u; }
+
+// A zeroed control block with epoch 1 (tag 0 is what never-written handoff words carry).
+// Caller holds g_mu.
+int alloc_control(int dev, Control** out) {
+  Control init;
+  std::memset(&init, 0, sizeof(init));
+  init.epoch = 1u;
+  init.fault = fault_of(dev);
+  Control* c = nullptr;
+  if (hipMalloc(&c, sizeof(Control)) != hipSuccess) return WF_E_NOMEM;
+  if (hipMemcpy(c, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(c);
+    return WF_E_DEVICE;
+  }
+  *out = c;
+  return WF_OK;
+}
+
 }  // namespace
 
-int ensure_ws(int dev, size_t words, DeviceWs** out) {
+int ensure_ws_on(int dev, hipStream_t s, size_t words, DeviceWs** out) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-  DeviceWs& w = g_ws[dev];
+  DeviceWs& w = g_ws[{dev, s}];
   if (!w.ctl) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return WF_E_DEVICE;
-    w.num_cus = prop.multiProcessorCount;
-    Control init;
-    std::memset(&init, 0, sizeof(init));
-    init.epoch = 1u;
-    if (hipMalloc(&w.ctl, sizeof(Control)) != hipSuccess) { w.ctl = nullptr; return WF_E_NOMEM; }
-    if (hipMemcpy(w.ctl, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) return WF_E_DEVICE;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      return WF_E_DEVICE;
+    w.num_cus = cus;
+    const int rc = alloc_control(dev, &w.ctl);
+    if (rc != WF_OK) {
+      w.ctl = nullptr;
+      return rc;
+    }
   }
   if (words > w.bnd_words) {
     // Growing: the old buffer may still be read by queued work, so drain the device first.
@@ -60,6 +85,26 @@ int ensure_ws(int dev, size_t words, DeviceWs** out) {
   }
   *out = &w;
   return WF_OK;
+}
+
+int ensure_ws(int dev, size_t words, DeviceWs** out) { return ensure_ws_on(dev, nullptr, words, out); }
+
+int new_control(int dev, Control** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int rc = alloc_control(dev, out);
+  if (rc == WF_OK) g_plan_ctl.emplace_back(dev, *out);
+  return rc;
+}
+
+void free_control(Control* ctl) {
+  if (!ctl) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (size_t i = 0; i < g_plan_ctl.size(); ++i)
+    if (g_plan_ctl[i].second == ctl) {
+      g_plan_ctl.erase(g_plan_ctl.begin() + (long)i);
+      break;
+    }
+  (void)hipFree(ctl);
 }
 
 // Grows the adjoint's selection buffer of a workspace that ensure_ws has set up.
@@ -137,6 +182,10 @@ int scratch_of(int dev, ScratchDev* out) {
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return WF_E_DEVICE;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      return WF_E_DEVICE;
+    // an injected fault mode (tests only) applies to the array's control block as well
+    const uint32_t f = fault_of(dev);
+    if (f && hipMemcpy(&reinterpret_cast<Control*>(p)->fault, &f, sizeof(f), hipMemcpyHostToDevice) != hipSuccess)
       return WF_E_DEVICE;
     sd.ptr = static_cast<char*>(p);
     sd.num_cus = cus;
@@ -261,7 +310,7 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
   const size_t words = (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * words_per_elem(dtype);
   DeviceWs* ws = nullptr;
-  int rc = ensure_ws(dev, words, &ws);
+  int rc = ensure_ws_on(dev, static_cast<hipStream_t>(stream), words, &ws);
   if (rc != WF_OK) return rc;
 
   FwdArgs a;
@@ -358,7 +407,7 @@ int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
   const size_t words = (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * 2 * words_per_elem(dtype);
   DeviceWs* ws = nullptr;
-  int rc = ensure_ws(dev, words, &ws);
+  int rc = ensure_ws_on(dev, static_cast<hipStream_t>(stream), words, &ws);
   if (rc != WF_OK) return rc;
   rc = ensure_sel(ws, (size_t)nb * (size_t)Ks * 64 * 8);
   if (rc != WF_OK) return rc;
@@ -425,9 +474,10 @@ int wf_reverse(int dtype, int64_t m, int64_t n, const void* g_score, const void*
   DeviceWs* ws = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (dev >= (int)g_ws.size()) return WF_E_ARG;
-    ws = &g_ws[dev];
-    // the selections in the workspace must be those of this shape and type
+    auto it = g_ws.find({dev, static_cast<hipStream_t>(stream)});
+    if (it == g_ws.end()) return WF_E_ARG;
+    ws = &it->second;
+    // the selections in this stream's workspace must be those of this shape and type
     if (ws->sel_dtype != dtype || ws->sel_m != m || ws->sel_n != n) return WF_E_ARG;
   }
   const int64_t nb = nbands(m);
@@ -496,7 +546,8 @@ int wf_soft_forward(int dtype, int64_t m, int64_t n, double gamma, const void* C
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
   DeviceWs* ws = nullptr;
-  rc = ensure_ws(dev, (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * words_per_elem(dtype), &ws);
+  rc = ensure_ws_on(dev, static_cast<hipStream_t>(stream), (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * words_per_elem(dtype),
+                    &ws);
   if (rc != WF_OK) return rc;
   SoftArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -530,7 +581,8 @@ int wf_soft_backward(int dtype, int64_t m, int64_t n, double gamma, const void* 
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
   DeviceWs* ws = nullptr;
-  rc = ensure_ws(dev, (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * 2 * words_per_elem(dtype), &ws);
+  rc = ensure_ws_on(dev, static_cast<hipStream_t>(stream),
+                    (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * 2 * words_per_elem(dtype), &ws);
   if (rc != WF_OK) return rc;
   SoftArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -590,13 +642,23 @@ int wf_fault_inject(int32_t mode) {
   if (mode < 0 || mode > (int32_t)kFaultRevWithhold) return WF_E_ARG;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
-  DeviceWs* ws = nullptr;
-  int rc = ensure_ws(dev, 1, &ws);
-  if (rc != WF_OK) return rc;
   // queued sweeps keep the mode they were launched under
   if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_fault.size() <= dev) g_fault.resize(dev + 1, 0u);
+  g_fault[dev] = (uint32_t)mode;
   const uint32_t v = (uint32_t)mode;
-  if (hipMemcpy(&ws->ctl->fault, &v, sizeof(v), hipMemcpyHostToDevice) != hipSuccess) return WF_E_DEVICE;
+  for (auto& kv : g_ws)
+    if (kv.first.first == dev && kv.second.ctl &&
+        hipMemcpy(&kv.second.ctl->fault, &v, sizeof(v), hipMemcpyHostToDevice) != hipSuccess)
+      return WF_E_DEVICE;
+  for (auto& pc : g_plan_ctl)
+    if (pc.first == dev && hipMemcpy(&pc.second->fault, &v, sizeof(v), hipMemcpyHostToDevice) != hipSuccess)
+      return WF_E_DEVICE;
+  if (dev < (int)g_scratch.size() && g_scratch[dev].ready &&
+      hipMemcpy(&reinterpret_cast<Control*>(g_scratch[dev].ptr)->fault, &v, sizeof(v), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return WF_E_DEVICE;
   return WF_OK;
 }
 
@@ -604,19 +666,18 @@ int wf_last_async_error(void* stream) {
   if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return WF_E_DEVICE;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
-  Control* ctl = nullptr;
+  // every control block of the device: the streams' workspaces, the plans', the scratch array's
+  std::vector<Control*> ctls;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (dev < (int)g_ws.size()) ctl = g_ws[dev].ctl;
-  }
-  Control* sctl = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (dev < (int)g_scratch.size() && g_scratch[dev].ready) sctl = reinterpret_cast<Control*>(g_scratch[dev].ptr);
+    for (auto& kv : g_ws)
+      if (kv.first.first == dev && kv.second.ctl) ctls.push_back(kv.second.ctl);
+    for (auto& pc : g_plan_ctl)
+      if (pc.first == dev) ctls.push_back(pc.second);
+    if (dev < (int)g_scratch.size() && g_scratch[dev].ready) ctls.push_back(reinterpret_cast<Control*>(g_scratch[dev].ptr));
   }
   uint32_t any = 0;
-  for (Control* c : {ctl, sctl}) {
-    if (!c) continue;
+  for (Control* c : ctls) {
     uint32_t err = 0;
     if (hipMemcpy(&err, &c->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return WF_E_DEVICE;
     if (err == 0) continue;

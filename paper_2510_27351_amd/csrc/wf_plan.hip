@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/wf.h"
+#include "wf_host.h"
 #include "wf_internal.h"
 
 using namespace wf;
@@ -26,7 +27,7 @@ struct wf_plan {
   int64_t elems = 0;
   int tile = 0, rows = 0;         // the configuration in use
   int num_cus = 0;
-  Control* ctl = nullptr;         // the device workspace's control block (shared, ordered)
+  Control* ctl = nullptr;         // the plan's own control block
   BatchInst* inst = nullptr;      // device copy of the instance table for 'rows'
   BatchItem* items = nullptr;     // device work list for 'rows'
   int32_t n_items = 0;
@@ -272,6 +273,7 @@ void free_plan(wf_plan* p) {
   if (p->b_items) (void)hipFree(p->b_items);
   if (p->b_sel) (void)hipFree(p->b_sel);
   if (p->b_bnd) (void)hipFree(p->b_bnd);
+  free_control(p->ctl);
   delete p;
 }
 
@@ -412,8 +414,13 @@ int wf_plan_create(wf_plan** out, int dtype, int32_t batch, const int64_t* m, co
     delete p;
     return rc;
   }
-  p->ctl = ws->ctl;
   p->num_cus = ws->num_cus;
+  rc = new_control(p->dev, &p->ctl);
+  if (rc != WF_OK) {
+    p->ctl = nullptr;
+    free_plan(p);
+    return rc;
+  }
   // handoff words: the one-row-per-band layout needs the most
   {
     std::vector<BatchInst> inst;
