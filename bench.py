@@ -7,15 +7,18 @@ Workload: one 16384 x 16384 float32 instance, values normal(0,1) clipped to [-4,
 (seed 2), resident in HBM before timing.  A step is the whole differentiable sweep:
   1. wf_forward: the table D, the score and the checkpoint grid (band rows every 64 rows,
      block columns every K = 64 columns), one persistent kernel;
-  2. wf_select: the predecessor selections recomputed from C and the checkpoint grid;
-  3. wf_reverse: the reverse sweep with g_score = 1 (the score's gradient).
-(2 and 3 together are wf_backward.)  Prints ONE JSON line: cells/s of the step (value),
-per-sweep cells/s and effective HBM rates (3 m n sizeof(elem) per sweep), per-kernel
-method-byte HBM rates measured with HIP events on the launch stream (the selection
-bit-planes passed from the recompute to the reverse sweep are reported apart, as
-intermediate traffic), the roofline entry of the kernel that takes the longest, the CPU
-oracle timed on a bounded sample on this host (the whole matrix when it fits the budget),
-and the error of this run's table, score and gradient against that oracle.  Also measured,
+  2. wf_backward with g_score = 1 and no g_D (the score's gradient): the selections
+     recomputed from C and the checkpoint grid together with the exits of every band's
+     last row and the zeroed gradient, the exits composed over groups of bands, and the
+     walk of the argmin path per band.
+Prints ONE JSON line: cells/s of the step (value), per-sweep cells/s and effective HBM
+rates (3 m n sizeof(elem) per sweep), method-byte HBM rates of the forward kernel and of
+the adjoint call measured with HIP events on the launch stream (the selection bit-planes
+and the exits, intermediates of the adjoint, are reported apart), the roofline entry of
+the one that takes the longest, the adjoint with an upstream gradient of the table (the
+reverse pipeline) timed beside it, the CPU oracle timed on a bounded sample on this host
+(the whole matrix when it fits the budget), and the error of this run's table, score and
+gradient against that oracle.  Also measured,
 as extra keys: the ragged batch (512 instances, one graph replay), the batched
 differentiable sweep (64 instances of 2048 x 2048, forward with checkpoints + adjoint), the
 smooth (soft-min) sweep of the same 16384 x 16384 matrix, and the tridiagonal partition
@@ -42,6 +45,8 @@ KERNELS = {
     "fwd_kernel": ("fwd_kernel_f32_16384_traffic.txt", ["wf_fwd.hip", "wf_common.h", "wf_internal.h"]),
     "sel_kernel": ("sel_kernel_f32_16384_traffic.txt", ["wf_bwd.hip", "wf_common.h", "wf_internal.h"]),
     "adj_kernel": ("adj_kernel_f32_16384_traffic.txt", ["wf_bwd.hip", "wf_common.h", "wf_internal.h"]),
+    "path_adjoint": ("path_adjoint_f32_16384_traffic.txt",
+                     ["wf_bwd.hip", "wf_common.h", "wf_internal.h", "wf_path.h", "wf_api.hip"]),
     "stage1_level0": ("tri_stage1_f64_1e8_traffic.txt", ["tri.hip"]),
     "stage3_level0": ("tri_stage3_f64_1e8_traffic.txt", ["tri.hip"]),
 }
@@ -402,11 +407,9 @@ def main():
         wf._lib.check(lib.wf_forward(code, m, n, C.data_ptr(), n, D.data_ptr(), n, wf_score.data_ptr(),
                                      ckpt.data_ptr(), CKPT_K, sp), "wf_forward")
 
-    def select():
-        wf._lib.check(lib.wf_select(code, m, n, C.data_ptr(), n, ckpt.data_ptr(), CKPT_K, None, n, sp), "wf_select")
-
-    def reverse():
-        wf._lib.check(lib.wf_reverse(code, m, n, one.data_ptr(), None, n, gC.data_ptr(), n, sp), "wf_reverse")
+    def bwd():
+        wf._lib.check(lib.wf_backward(code, m, n, C.data_ptr(), n, ckpt.data_ptr(), CKPT_K, None, n, one.data_ptr(),
+                                      None, n, gC.data_ptr(), n, sp), "wf_backward")
 
     wf_score = torch.empty((), dtype=C.dtype, device=dev)
     if args.calib_copy:
@@ -414,12 +417,11 @@ def main():
         torch.cuda.synchronize()
     for _ in range(args.warmup):
         fwd()
-        select()
-        reverse()
+        bwd()
     wf.last_async_error()
     torch.cuda.synchronize()
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -428,17 +430,13 @@ def main():
         ev[k][0].record(stream)
         fwd()
         ev[k][1].record(stream)
-        select()
+        bwd()
         ev[k][2].record(stream)
-        reverse()
-        ev[k][3].record(stream)
     t_end.record(stream)
     torch.cuda.synchronize()
     wf.last_async_error()
     total_ms = t_start.elapsed_time(t_end)
-    seg = [sum(e[i].elapsed_time(e[i + 1]) for e in ev) / K for i in range(3)]
-    fwd_ms, sel_ms, rev_ms = seg
-    bwd_ms = sel_ms + rev_ms
+    fwd_ms, bwd_ms = [sum(e[i].elapsed_time(e[i + 1]) for e in ev) / K for i in range(2)]
     ms = total_ms / K
     cells = m * n
     es = C.element_size()
@@ -447,15 +445,30 @@ def main():
     Ks = (n + 63 + 63) // 64
     plane_bytes = nb * Ks * 64 * 32  # selection bit-planes: 32 bytes per band row and 64 slots
     top_bytes = (nb - 1) * n * es     # band top rows read back from the checkpoint grid
-    # Method bytes per launch: the inputs and outputs of the differentiable sweep each kernel
-    # must move at least.  The selection bit-planes that the recompute writes and the reverse
-    # sweep reads are an intermediate of this implementation, reported apart.
+    exit_bytes = nb * n * 4           # exits of every band's last row
+    # The general adjoint (an upstream gradient of the table given: the reverse pipeline),
+    # timed beside the step on the same matrix with a zero g_D.
+    gD = torch.zeros_like(C)
+
+    def bwd_general():
+        wf._lib.check(lib.wf_backward(code, m, n, C.data_ptr(), n, ckpt.data_ptr(), CKPT_K, None, n, one.data_ptr(),
+                                      gD.data_ptr(), n, gC.data_ptr(), n, sp), "wf_backward")
+
+    bwd_general()
+    gen_ms = _events_ms(stream, bwd_general, max(2, min(K, 5)))
+    wf.last_async_error()
+    del gD
+    bwd()  # the step's own gradient for the error report
+    torch.cuda.synchronize()
+    # Method bytes per launch: the inputs and outputs of the differentiable sweep each launch
+    # must move at least.  The adjoint call's intermediates (selection bit-planes and exits,
+    # written by its sweep and read by its walk) are reported apart.
     kern = {
         "fwd_kernel": (fwd_ms, 2 * cells * es + ck_bytes, 0, "read C, write D and the checkpoint grid"),
-        "sel_kernel": (sel_ms, cells * es + top_bytes, plane_bytes,
-                       "read C and the checkpoint grid's band rows (intermediate: writes the selection bit-planes)"),
-        "adj_kernel": (rev_ms, cells * es, plane_bytes,
-                       "write g_C, no g_D given (intermediate: reads the selection bit-planes)"),
+        "path_adjoint": (bwd_ms, 2 * cells * es + top_bytes, plane_bytes + exit_bytes,
+                         "wf_backward, score alone (sel_path_kernel + compose_kernel + walk_kernel): read C and "
+                         "the checkpoint grid's band rows, write g_C (intermediate: the selection bit-planes "
+                         "and the exits written)"),
     }
     eff = lambda nbytes, t_ms: nbytes / (t_ms * 1e-3) / 1e9  # noqa: E731
     kernels = {k: {"ms": t, "bytes_per_launch": b, "intermediate_bytes_per_launch": ib,
@@ -478,15 +491,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single {m}x{n} float32, normal(0,1) clipped to [-4,4], seed 2; step = "
                                f"forward (table, score, checkpoint grid K={CKPT_K}) + adjoint of the score "
-                               "from the checkpoint grid (selection recompute + reverse sweep)",
+                               "from the checkpoint grid (wf_backward: selection recompute with the bands' "
+                               "exits, then the walk of the argmin path)",
                    "m": m, "n": n, "ckpt_k": CKPT_K,
                    "tile_forward": wf.predict_tile(m, n), "tile_reverse": wf.predict_tile(m, n, reverse=True)},
         "fwd": {"ms": fwd_ms, "cells_per_s": cells / (fwd_ms * 1e-3),
                 "effective_GBps": eff(3 * cells * es, fwd_ms),
                 "effective_pct_peak": 100 * eff(3 * cells * es, fwd_ms) / PEAK_HBM_GBPS},
-        "adjoint": {"ms": bwd_ms, "select_ms": sel_ms, "reverse_ms": rev_ms, "cells_per_s": cells / (bwd_ms * 1e-3),
+        "adjoint": {"ms": bwd_ms, "cells_per_s": cells / (bwd_ms * 1e-3),
                     "effective_GBps": eff(3 * cells * es, bwd_ms),
                     "effective_pct_peak": 100 * eff(3 * cells * es, bwd_ms) / PEAK_HBM_GBPS},
+        "adjoint_with_gD": {"ms": gen_ms, "cells_per_s": cells / (gen_ms * 1e-3),
+                            "note": "wf_backward with an upstream gradient of the table (zero here): selection "
+                                    "recompute then the reverse pipeline; not part of the step"},
         "fwd_adjoint": {"ms": ms, "effective_GBps": eff(6 * cells * es, ms),
                         "effective_pct_peak": 100 * eff(6 * cells * es, ms) / PEAK_HBM_GBPS},
         "kernels": kernels,

@@ -18,6 +18,7 @@
 #include "../../include/wf.h"
 #include "wf_host.h"
 #include "wf_internal.h"
+#include "wf_path.h"
 #include "wf_soft.h"
 
 namespace wf {
@@ -105,6 +106,45 @@ void free_control(Control* ctl) {
       break;
     }
   (void)hipFree(ctl);
+}
+
+// Buffers of the path adjoint of one (device, stream): exits, captured labels, group maps.
+struct PathWs {
+  int32_t* exits = nullptr;
+  size_t exits_words = 0;
+  int32_t* caps = nullptr;
+  size_t caps_words = 0;
+  int32_t* F = nullptr;
+  size_t F_words = 0;
+};
+std::map<std::pair<int, hipStream_t>, PathWs> g_path;
+
+// Grows a device buffer to at least 'words' 32-bit words (drains the device before freeing
+// the old one, which queued work may still read).  Caller holds g_mu.
+int grow_words(int32_t** p, size_t* have, size_t words) {
+  if (words <= *have) return WF_OK;
+  if (*p) {
+    if (hipDeviceSynchronize() != hipSuccess) return WF_E_DEVICE;
+    (void)hipFree(*p);
+  }
+  *p = nullptr;
+  *have = 0;
+  if (hipMalloc(p, words * sizeof(int32_t)) != hipSuccess) {
+    *p = nullptr;
+    return WF_E_NOMEM;
+  }
+  *have = words;
+  return WF_OK;
+}
+
+int ensure_path(int dev, hipStream_t s, size_t exits, size_t caps, size_t F, PathWs** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  PathWs& w = g_path[{dev, s}];
+  int rc = grow_words(&w.exits, &w.exits_words, exits);
+  if (rc == WF_OK) rc = grow_words(&w.caps, &w.caps_words, caps);
+  if (rc == WF_OK) rc = grow_words(&w.F, &w.F_words, F > 0 ? F : 1);
+  *out = &w;
+  return rc;
 }
 
 // Grows the adjoint's selection buffer of a workspace that ensure_ws has set up.
@@ -382,8 +422,14 @@ int wf_forward_noalloc(int dtype, int64_t m, int64_t n, const void* C, int64_t l
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
 
-int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt, int32_t ckpt_k,
-              const void* D, int64_t ldd, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks the arguments of a selection recompute, sets up the stream's workspace and fills
+// the launch's arguments and grid (wf_select and the path adjoint).
+int prepare_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt, int32_t ckpt_k,
+                   const void* D, int64_t ldd, void* stream, DeviceWs** out, SelArgs* sel_args, int* grid_out) {
   if (dtype != WF_F32 && dtype != WF_F64) return dtype == WF_I32 ? WF_E_UNSUPPORTED : WF_E_ARG;
   const int es = elem_size(dtype);
   if (m < 1 || n < 1 || n > (int64_t)1 << 31 || m > (int64_t)1 << 40) return WF_E_ARG;
@@ -411,7 +457,6 @@ int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const
   if (rc != WF_OK) return rc;
   rc = ensure_sel(ws, (size_t)nb * (size_t)Ks * 64 * 8);
   if (rc != WF_OK) return rc;
-  hipStream_t st = static_cast<hipStream_t>(stream);
 
   SelArgs sa;
   sa.C = C;
@@ -452,11 +497,33 @@ int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const
   sa.nb = (int32_t)nb;
   sa.sel = ws->sel;
   sa.ctl = ws->ctl;
-  if (launch_select(dtype, sa, grid, st) != hipSuccess) return WF_E_DEVICE;
+  *out = ws;
+  *sel_args = sa;
+  *grid_out = grid;
+  return WF_OK;
+}
+
+// Records that the stream's workspace now holds the selections of this shape and type.
+void note_selections(DeviceWs* ws, int dtype, int64_t m, int64_t n) {
   std::lock_guard<std::mutex> lk(g_mu);
   ws->sel_dtype = dtype;
   ws->sel_m = m;
   ws->sel_n = n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wf_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt, int32_t ckpt_k,
+              const void* D, int64_t ldd, void* stream) {
+  DeviceWs* ws = nullptr;
+  SelArgs sa;
+  int grid = 0;
+  const int rc = prepare_select(dtype, m, n, C, ldc, ckpt, ckpt_k, D, ldd, stream, &ws, &sa, &grid);
+  if (rc != WF_OK) return rc;
+  if (launch_select(dtype, sa, grid, static_cast<hipStream_t>(stream)) != hipSuccess) return WF_E_DEVICE;
+  note_selections(ws, dtype, m, n);
   return WF_OK;
 }
 
@@ -515,9 +582,51 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
                  : (D == nullptr || ckpt != nullptr || ldd < n))
     return WF_E_ARG;
   if (ldc > kMaxLd / es || ldgc > kMaxLd / es || (g_D && ldgd > kMaxLd / es)) return WF_E_UNSUPPORTED;
-  int rc = wf_select(dtype, m, n, C, ldc, ckpt, ckpt_k, D, ldd, stream);
+  if (g_D) {
+    const int rc = wf_select(dtype, m, n, C, ldc, ckpt, ckpt_k, D, ldd, stream);
+    if (rc != WF_OK) return rc;
+    return wf_reverse(dtype, m, n, g_score, g_D, ldgd, g_C, ldgc, stream);
+  }
+  // The score alone: its upstream value on the argmin path, zero elsewhere.
+  DeviceWs* ws = nullptr;
+  SelArgs sa;
+  int grid = 0;
+  int rc = prepare_select(dtype, m, n, C, ldc, ckpt, ckpt_k, D, ldd, stream, &ws, &sa, &grid);
   if (rc != WF_OK) return rc;
-  return wf_reverse(dtype, m, n, g_score, g_D, ldgd, g_C, ldgc, stream);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nb = sa.nb;
+  const int32_t S = nb > 1 ? std::max<int32_t>(1, (int32_t)std::ceil(std::sqrt((double)(nb - 1)))) : 1;
+  const int32_t G = nb > 1 ? (nb - 1 + S - 1) / S : 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
+  PathWs* pw = nullptr;
+  rc = ensure_path(dev, st, (size_t)nb * (size_t)n, (size_t)nb * 2 * 64, (size_t)G * (size_t)n, &pw);
+  if (rc != WF_OK) return rc;
+  // The gradient is zeroed by the sweep itself for float32 (its zero stores cost the sweep
+  // less than a pass of their own) and by a pass of its own before it for float64 (twice the
+  // bytes: the fused stores slowed the sweep by more than the pass takes).
+  const bool fused = dtype == WF_F32;
+  if (!fused && launch_zero(dtype, g_C, m, n, ldgc, 8 * ws->num_cus, st) != hipSuccess) return WF_E_DEVICE;
+  if (launch_select_path(dtype, sa, PathLabels{pw->exits, pw->caps, fused ? g_C : nullptr, ldgc}, grid, st) !=
+      hipSuccess)
+    return WF_E_DEVICE;
+  note_selections(ws, dtype, m, n);
+  PathArgs pa;
+  pa.exits = pw->exits;
+  pa.caps = pw->caps;
+  pa.F = pw->F;
+  pa.sel = ws->sel;
+  pa.gscore = g_score;
+  pa.gC = g_C;
+  pa.ldgc = ldgc;
+  pa.m = m;
+  pa.n = n;
+  pa.split = sa.split;
+  pa.nb = nb;
+  pa.Ks = (int32_t)((n + kBand - 1 + 63) / 64);
+  pa.S = S;
+  pa.G = G;
+  return launch_path(dtype, pa, st) == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
 
 namespace {

@@ -28,7 +28,10 @@
 // Waves of the reverse sweep: compute; value loader (gD); factor loader (bit-planes ->
 // factors); poller (values from the band below); storer (gC); publisher (values for the
 // band above).
+#include <algorithm>
+
 #include "wf_common.h"
+#include "wf_path.h"
 
 namespace wf {
 namespace {
@@ -137,10 +140,43 @@ __device__ __forceinline__ SelPiece sel_piece(const SelArgs& a, int piece, int K
 
 // One sub-chunk of the compute wave (see sel_compute); ENTRY: the first sub-chunk of a
 // band's second piece, where each row takes its left value and nothing is stored.
-template <typename T, bool ENTRY>
+// Cache policy of the gradient's zero stores (gfx950 buffer instructions: bit 1 = nt).
+constexpr int kZeroAux = 2;
+
+// Label state of the path variant (LAB): the exit of the lane's previous cell (W of the next
+// cell), the previous N label, lane 0's N label (the cell's column below a band, -1 in band
+// 0) and its step, lane 63's labels of the sub-chunk shifted in one per step, and the label
+// captured at slot cbase + lane (CAP sub-chunks).
+struct LabState {
+  int32_t LX, LNW, tcol, inc, acc, cap, cbase;
+};
+
+// Selection bits and the label of one cell: N if N < NW, W if W < min(N, NW), else NW.
+__device__ __forceinline__ void sel_bits_lab(uint32_t& pn, uint32_t& pw, float N, float NW, float X, float m,
+                                             int32_t LN, int32_t LNW, int32_t LX, int32_t& L) {
+  int32_t t;
+  asm("v_cmp_lt_f32 vcc, %4, %5\n\t"
+      "v_cndmask_b32 %0, %8, %7, vcc\n\t"
+      "v_addc_co_u32 %2, vcc, %2, %2, vcc\n\t"
+      "v_cmp_lt_f32 vcc, %6, %10\n\t"
+      "v_cndmask_b32 %1, %0, %9, vcc\n\t"
+      "v_addc_co_u32 %3, vcc, %3, %3, vcc"
+      : "=&v"(t), "=&v"(L), "+v"(pn), "+v"(pw)
+      : "v"(N), "v"(NW), "v"(X), "v"(LN), "v"(LNW), "v"(LX), "v"(m)
+      : "vcc");
+}
+__device__ __forceinline__ void sel_bits_lab(uint32_t& pn, uint32_t& pw, double N, double NW, double X, double m,
+                                             int32_t LN, int32_t LNW, int32_t LX, int32_t& L) {
+  const bool nl = N < NW, wl = X < m;
+  pn = pn + pn + (uint32_t)nl;
+  pw = pw + pw + (uint32_t)wl;
+  L = wl ? LX : (nl ? LN : LNW);
+}
+
+template <typename T, bool ENTRY, bool LAB = false, bool CAP = false>
 __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __restrict__ Tr, const SelArgs& a, int band,
                                         int Ks, int k, int rows, int64_t n, T& X, T& NW, T left,
-                                        SelGroup<T> (&P)[2]) {
+                                        SelGroup<T> (&P)[2], LabState& ls, const PathLabels& po) {
   using C = BCfg<T>;
   using E = typename C::E;
   typedef int v4i __attribute__((ext_vector_type(4)));
@@ -154,6 +190,19 @@ __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __rest
   gr[1] = P[1];
   uint32_t pl[3][2];
   uint32_t pw = 0, pn = 0;
+  // CAP: lane r captures its label at slot cbase + r, i.e. at step 4g + q == cl of the sub-chunk
+  const int cl = CAP ? lane - (kSub * k - ls.cbase) : 0;
+  // LAB with a gradient to zero: after the sweep, 16-byte zeros over columns [64k, 64k + 64)
+  // when they all lie in the matrix (rows past the band's last fall outside the buffer
+  // range and are dropped), else element by element
+  const bool zfast = LAB && !ENTRY && po.gC != nullptr && (int64_t)kSub * k + kSub <= n;
+  __amdgpu_buffer_rsrc_t zrs = make_rsrc(nullptr, 0u);
+  int zoff = 0;
+  if (zfast) {
+    zrs = make_rsrc(static_cast<T*>(po.gC) + (int64_t)band * kBand * po.ldgc,
+                    (uint32_t)(((rows - 1) * po.ldgc + n) * (int64_t)sizeof(T)));
+    zoff = (int)(((int64_t)(lane >> 4) * po.ldgc + (int64_t)kSub * k + 4 * (lane & 15)) * (int64_t)sizeof(T));
+  }
 #pragma unroll
   for (int g = 0; g < 16; ++g) {
     if (g + 2 < 16)
@@ -167,12 +216,27 @@ __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __rest
     for (int q = 0; q < 4; ++q) {
       const T N = E::shr1(X, gr[g].t.v[q]);
       const T m = sel_min(NW, N);
-      sel_bit(pn, N, NW);
-      sel_bit(pw, X, m);
+      if constexpr (LAB) {
+        const int32_t LN = Elem<int32_t>::shr1(ls.LX, ls.tcol);
+        int32_t L;
+        sel_bits_lab(pn, pw, N, NW, X, m, LN, ls.LNW, ls.LX, L);
+        ls.LNW = LN;
+        ls.LX = L;
+        ls.acc = (int32_t)dpp_shl1_u32((uint32_t)ls.acc, (uint32_t)L);
+        ls.tcol += ls.inc;
+        if (CAP && 4 * g + q == cl) ls.cap = L;
+      } else {
+        sel_bit(pn, N, NW);
+        sel_bit(pw, X, m);
+      }
       X = E::add(gr[g].c.v[q], sel_min(m, X));
       NW = N;
-      if (ENTRY && 4 * g + q == lane - 1) X = left;
+      if (ENTRY && 4 * g + q == lane - 1) {
+        X = left;
+        if constexpr (LAB) ls.LX = -2 - lane;
+      }
     }
+
     if ((g & 7) == 7) {
       const int h = g >> 3;
       pw = __builtin_bitreverse32(pw);
@@ -206,6 +270,35 @@ __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __rest
     v4i* dst = reinterpret_cast<v4i*>(out + sel_index(band, Ks, k, lane));
     __builtin_nontemporal_store(w0, dst);
     __builtin_nontemporal_store(w1, dst + 1);
+    if constexpr (LAB) {
+      // lane r holds lane 63's label of slot 64k + r: the last row's cell of column 64k + r - 63
+      const int64_t col = (int64_t)kSub * k + lane - 63;
+      if (col >= 0 && col < n) po.exits[(int64_t)band * n + col] = ls.acc;
+      // zeros over the gradient's columns [64k, 64k + 64) of the band's rows (the second
+      // piece's first sub-chunk is the first piece's last); rows past the band's last fall
+      // outside the buffer range and are dropped
+      if (po.gC == nullptr) return;
+      if (zfast) {
+        // streaming (non-temporal) stores: the zeros are not read back by this sweep
+        const v4i z = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int off = zoff + (int)((int64_t)(4 * q) * po.ldgc * (int64_t)sizeof(T));
+          __builtin_amdgcn_raw_buffer_store_b128(z, zrs, off, 0, kZeroAux);
+          if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b128(z, zrs, off + 16, 0, kZeroAux);
+        }
+        return;
+      }
+      const int64_t c0 = (int64_t)kSub * k + 4 * (lane & 15);
+      T* gb = static_cast<T*>(po.gC) + (int64_t)band * kBand * po.ldgc;
+      for (int q = 0; q < 16; ++q) {
+        const int i = 4 * q + (lane >> 4);
+        if (i >= rows) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (c0 + e < n) gb[(int64_t)i * po.ldgc + c0 + e] = T(0);
+      }
+    }
   }
 }
 
@@ -216,9 +309,9 @@ __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __rest
 // row r's state enters as column split-1 of the forward table, which the wave sets at step
 // r-1 (row 0 before the first step, its NW from the row above); the cells before it are
 // none of this piece's and their selections are not stored.
-template <typename T>
+template <typename T, bool LAB>
 __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __restrict__ Tr, SelShared& sh,
-                                            const SelArgs& a, int band, int Ks, SelPiece pc) {
+                                            const SelArgs& a, int band, int Ks, SelPiece pc, const PathLabels& po) {
   using C = BCfg<T>;
   using E = typename C::E;
   const int lane = threadIdx.x & 63;
@@ -234,6 +327,27 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
     if (lane == 0) {
       X = left;
       NW = band > 0 ? static_cast<const T*>(a.top)[(int64_t)(band - 1) * a.ld_top + c] : E::inf();
+    }
+  }
+  // labels (LAB): -1 (leaves the matrix) before the first column; lane 0's N label is the
+  // cell's own column below band 0; the second piece's rows enter with -2 - r
+  LabState ls;
+  bool has_cap = false;
+  if constexpr (LAB) {
+    const int64_t c0 = pc.second ? opaque(a.split) : 0;
+    ls.inc = band > 0 ? 1 : 0;
+    ls.tcol = band > 0 ? (int32_t)c0 : -1;
+    ls.LX = (pc.second && lane == 0) ? -2 : -1;
+    ls.LNW = (pc.second && lane == 0 && band > 0) ? (int32_t)(c0 - 1) : -1;
+    ls.acc = 0;
+    ls.cap = -1;
+    ls.cbase = 0;
+    if (a.split > 0 && !pc.second) {
+      has_cap = true;
+      ls.cbase = (int32_t)(a.split - 1);
+    } else if (band == a.nb - 1) {
+      has_cap = true;
+      ls.cbase = (int32_t)(n - 1);
     }
   }
   uint64_t waited = 0;
@@ -254,10 +368,15 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
       for (int p = 0; p < 2; ++p) sel_load_group<T>(S, Tr, base + 4 * p, lane, P[p]);
     }
     if (pc.second && k == pc.k0)
-      sel_sub<T, true>(S, Tr, a, band, Ks, k, rows, n, X, NW, left, P);
+      sel_sub<T, true, LAB>(S, Tr, a, band, Ks, k, rows, n, X, NW, left, P, ls, po);
+    else if (LAB && has_cap && (int64_t)kSub * k + 63 >= ls.cbase && (int64_t)kSub * k <= (int64_t)ls.cbase + 63)
+      sel_sub<T, false, LAB, true>(S, Tr, a, band, Ks, k, rows, n, X, NW, left, P, ls, po);
     else
-      sel_sub<T, false>(S, Tr, a, band, Ks, k, rows, n, X, NW, left, P);
+      sel_sub<T, false, LAB>(S, Tr, a, band, Ks, k, rows, n, X, NW, left, P, ls, po);
     lds_signal(&sh.steps, (uint32_t)(kSub * (kl + 1)));
+  }
+  if constexpr (LAB) {
+    if (has_cap) po.caps[((int64_t)band * 2 + (pc.second ? 1 : 0)) * 64 + lane] = ls.cap;
   }
 }
 
@@ -378,14 +497,15 @@ struct SelLds {
 
 // One work item: band 'band' (piece 'piece' of it when the band is split) of the instance
 // 'a' describes.  The LDS counters must be zero on entry.
-template <typename T>
-__device__ __forceinline__ void sel_item(SelLds<T>& L, SelShared& sh, const SelArgs& a, int band, int piece) {
+template <typename T, bool LAB = false>
+__device__ __forceinline__ void sel_item(SelLds<T>& L, SelShared& sh, const SelArgs& a, int band, int piece,
+                                         const PathLabels& po = PathLabels{nullptr, nullptr, nullptr, 0}) {
   T* S = reinterpret_cast<T*>(L.S4);
   T* Tr = reinterpret_cast<T*>(L.Tr4);
   const int Ks = (int)((a.n + kBand - 1 + kSub - 1) / kSub);
   const SelPiece pc = sel_piece(a, piece, Ks);
   if (threadIdx.x < 64)
-    sel_compute<T>(S, Tr, sh, a, band, Ks, pc);
+    sel_compute<T, LAB>(S, Tr, sh, a, band, Ks, pc, po);
   else
     sel_loader<T>(S, Tr, sh, a, band, Ks, pc);
 }
@@ -1205,6 +1325,144 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adj_batch_kernel(BwdBatchArgs 
   finish_launch(ctl, epoch);
 }
 
+// =======================================================================================
+// 3. Adjoint of the score alone by the argmin path (no upstream gradient of the table).
+// =======================================================================================
+
+// The selection recompute with the exits of every band's last row (and the captured
+// labels) besides the bit-planes; otherwise sel_kernel.
+template <typename T>
+__global__ __launch_bounds__(128, 1) void sel_path_kernel(SelArgs a, PathLabels po) {
+  __shared__ SelLds<T> L;
+  __shared__ SelShared sh;
+  Control* ctl = a.ctl;
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) sh.abort = 0u;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      sh.loaded = 0u;
+      sh.steps = 0u;
+    }
+    claim_next(ctl, &sh.item, &sh.abort);
+    const int pieces = a.split > 0 ? 2 : 1;
+    const int item = (int)sh.item;
+    if (item >= a.nb * pieces || sh.abort != 0u) break;
+    sel_item<T, true>(L, sh, a, item / pieces, item % pieces, po);
+    __syncthreads();
+  }
+  finish_launch(ctl, epoch);
+}
+
+// Zeroes an m x n matrix of leading dimension ld: rows over the grid, 16-byte stores along a
+// row when the rows are 16-byte aligned.
+template <typename T>
+__global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ p, int64_t m, int64_t n, int64_t ld, int vec) {
+  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+    T* row = p + i * ld;
+    int64_t j0 = 0;
+    if (vec) {
+      const int64_t nv = n * (int64_t)sizeof(T) / 16;
+      uint4* r4 = reinterpret_cast<uint4*>(row);
+      for (int64_t j = threadIdx.x; j < nv; j += blockDim.x) r4[j] = make_uint4(0u, 0u, 0u, 0u);
+      j0 = nv * 16 / (int64_t)sizeof(T);
+    }
+    for (int64_t j = j0 + threadIdx.x; j < n; j += blockDim.x) row[j] = T(0);
+  }
+}
+
+// An exit as stored (a column, -1, or -2 - r of a split band's second piece) made a column
+// or -1; anything out of range reads as -1.
+__device__ __forceinline__ int32_t path_resolve(const PathArgs& a, int b, int32_t v) {
+  if (v <= -2) v = v >= -65 ? a.caps[(int64_t)b * 2 * 64 + (-2 - v)] : -1;
+  return (v >= 0 && v < a.n) ? v : -1;
+}
+
+// F[g][p] for the groups g >= 1: the path entering the last band of group g at column p,
+// followed up through the group's bands.
+__global__ __launch_bounds__(256) void compose_kernel(PathArgs a) {
+  const int g = (int)blockIdx.y + 1;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  const int lo = g * a.S;
+  const int hi = (lo + a.S < a.nb - 1 ? lo + a.S : a.nb - 1) - 1;
+  int32_t v = (int32_t)p;
+  for (int b = hi; b >= lo && v >= 0; --b) v = path_resolve(a, b, a.exits[(int64_t)b * a.n + v]);
+  a.F[(int64_t)g * a.n + p] = v;
+}
+
+// One wave per band: the column at which the path enters the band's last row (the last
+// cell for the last band; otherwise the end cell's exit followed down through the groups
+// and then through the bands of the band's own group), then the walk up the band along the
+// selections, writing the score's upstream value on every cell of the path.  The rows'
+// runs of path cells are written by the lanes at once.
+template <typename T>
+__global__ __launch_bounds__(64) void walk_kernel(PathArgs a) {
+  const int b = (int)blockIdx.x;
+  const int lane = (int)threadIdx.x;
+  T gv = a.gscore ? *static_cast<const T*>(a.gscore) : T(0);
+  gv = gv + T(0);  // the last cell's value is 0 + gscore
+  if (gv == T(0)) return;
+  const int nb = a.nb;
+  const int64_t n = a.n;
+  const int rows_last = (int)(a.m - (int64_t)(nb - 1) * kBand);
+  int32_t q = (int32_t)(n - 1);
+  if (b < nb - 1) {
+    const int endp = a.split > 0 ? 1 : 0;
+    q = path_resolve(a, nb - 1, a.caps[((int64_t)(nb - 1) * 2 + endp) * 64 + rows_last - 1]);
+    const int gb = b / a.S;
+    for (int g = (nb - 2) / a.S; g > gb && q >= 0; --g) {
+      q = a.F[(int64_t)g * n + q];
+      q = (q >= 0 && q < n) ? q : -1;
+    }
+    const int btop = (gb * a.S + a.S < nb - 1 ? gb * a.S + a.S : nb - 1) - 1;
+    for (int bb = btop; bb > b && q >= 0; --bb) q = path_resolve(a, bb, a.exits[(int64_t)bb * n + q]);
+  }
+  q = __builtin_amdgcn_readfirstlane(q);
+  if (q < 0) return;
+  const int rows = b == nb - 1 ? rows_last : kBand;
+  T* g0 = static_cast<T*>(a.gC) + (int64_t)b * kBand * a.ldgc;
+  const uint32_t* planes = a.sel;
+  int r = rows - 1;
+  int64_t col = q;
+  int64_t run_hi = col;
+  int kcur = -1;
+  uint32_t w[6] = {0u, 0u, 0u, 0u, 0u, 0u};
+  auto flush = [&](int row, int64_t lo, int64_t hi) {
+    for (int64_t c = lo + lane; c <= hi; c += 64) g0[(int64_t)row * a.ldgc + c] = gv;
+  };
+  for (;;) {
+    const int64_t s = col + r;
+    const int k = (int)(s >> 6);
+    if (k != kcur) {
+      const uint4* src = reinterpret_cast<const uint4*>(planes + sel_index(b, a.Ks, k, lane));
+      const uint4 x0 = src[0], x1 = src[1];
+      w[0] = x0.x; w[1] = x0.y; w[2] = x0.z; w[3] = x0.w; w[4] = x1.x; w[5] = x1.y;
+      kcur = k;
+    }
+    const int j = (int)(s & 63), h = j >> 5, bit = j & 31;
+    const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(h ? w[1] : w[0]), r);
+    const uint32_t sn = (uint32_t)__builtin_amdgcn_readlane((int)(h ? w[3] : w[2]), r);
+    const uint32_t snw = (uint32_t)__builtin_amdgcn_readlane((int)(h ? w[5] : w[4]), r);
+    if ((sw >> bit) & 1u) {
+      if (col == 0) break;  // never selected: W of column 0 is outside the matrix
+      --col;
+      continue;
+    }
+    flush(r, col, run_hi);
+    if ((sn >> bit) & 1u) {
+      if (r == 0) break;  // into the band above
+      --r;
+    } else if ((snw >> bit) & 1u) {
+      if (r == 0 || col == 0) break;  // into the band above, or outside the matrix
+      --r;
+      --col;
+    } else {
+      break;  // cell (0, 0)
+    }
+    run_hi = col;
+  }
+}
+
 template <typename T, bool TRACE>
 hipError_t launch_adj_tt(int tile, const AdjArgs& a, int grid, hipStream_t s) {
   switch (tile) {
@@ -1238,6 +1496,41 @@ hipError_t launch_adjoint(int dtype, int tile, const AdjArgs& a, int grid, hipSt
     case 1: return launch_adj_t<double>(tile, a, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_select_path(int dtype, const SelArgs& a, const PathLabels& p, int grid, hipStream_t s) {
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL((sel_path_kernel<float>), dim3(grid), dim3(128), 0, s, a, p); break;
+    case 1: hipLaunchKernelGGL((sel_path_kernel<double>), dim3(grid), dim3(128), 0, s, a, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int dtype, void* p, int64_t m, int64_t n, int64_t ld, int grid, hipStream_t s) {
+  const int es = dtype == 1 ? 8 : 4;
+  const int vec = ((uintptr_t)p % 16 == 0 && (ld * es) % 16 == 0) ? 1 : 0;
+  const int g = (int)std::min<int64_t>(m, grid);
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL((zero_kernel<float>), dim3(g), dim3(256), 0, s, static_cast<float*>(p), m, n, ld, vec); break;
+    case 1: hipLaunchKernelGGL((zero_kernel<double>), dim3(g), dim3(256), 0, s, static_cast<double*>(p), m, n, ld, vec); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_path(int dtype, const PathArgs& a, hipStream_t s) {
+  if (a.G > 1) {
+    hipLaunchKernelGGL(compose_kernel, dim3((unsigned)((a.n + 255) / 256), (unsigned)(a.G - 1)), dim3(256), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL((walk_kernel<float>), dim3(a.nb), dim3(64), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((walk_kernel<double>), dim3(a.nb), dim3(64), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_select_batch(int dtype, const BwdBatchArgs& b, int grid, hipStream_t s) {

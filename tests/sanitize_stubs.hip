@@ -2,6 +2,7 @@
 // place of the kernel sources: every call the driver makes fails its argument checks before
 // any launch, so these are never called.  forward_band_rows returns the library's value (one
 // 64-row sub-band per band), which the checks use.
+#include "../paper_2510_27351_amd/csrc/wf_path.h"
 #include "../paper_2510_27351_amd/csrc/wf_soft.h"
 
 namespace wf {
@@ -10,5 +11,8 @@ hipError_t launch_select(int, const SelArgs&, int, hipStream_t) { return hipErro
 hipError_t launch_adjoint(int, int, const AdjArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_soft_forward(int, const SoftArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_soft_backward(int, const SoftArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_select_path(int, const SelArgs&, const PathLabels&, int, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_zero(int, void*, int64_t, int64_t, int64_t, int, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_path(int, const PathArgs&, hipStream_t) { return hipErrorInvalidValue; }
 int forward_band_rows(int) { return kBand; }
 }  // namespace wf

@@ -63,12 +63,15 @@ def test_reverse_wait_expires_then_recovers(oracle_mod):
     print("reverse sweep with the bottom band withholding its values (expect one 2 s wait)", flush=True)
     inject(2)
     try:
-        wf.backward(Cd, g_score=one, D=D)
+        # the reverse pipeline itself (wf_backward of the score alone walks the argmin path)
+        wf.select(Cd, D=D)
+        wf.reverse(300, 200, torch.float32, g_score=one)
         torch.cuda.synchronize()
     finally:
         inject(0)
     expect_timeout()
-    g = wf.backward(Cd, g_score=one, D=D)
+    wf.select(Cd, D=D)
+    g = wf.reverse(300, 200, torch.float32, g_score=one)
     wf.last_async_error()
     _, sel = oracle_mod.forward(C.numpy(), "f32", want_sel=True)
     ref = oracle_mod.backward(sel, None, 1.0, "f32")

@@ -1,0 +1,130 @@
+"""The adjoint of the score alone on the GPU: wf_backward with no upstream gradient of the
+table finds the argmin path (exits of every band's last row, composed over groups of bands,
+then a walk per band) instead of running the reverse pipeline.
+
+Bars: bitwise equal to the oracle's routed adjoint on the oracle's own selection map in the
+same precision (with no g_D every value is 0 or 0 + gscore, exact in any order), and bitwise
+equal to the reverse pipeline (wf_select then wf_reverse) on the same stream.  The cases
+cover one-cell, one-row and one-column matrices, partial last bands, more bands than
+compute units, split bands (two column pieces per band, whose second piece's exits name rows
+of the split column), every source of the band rows, heavy ties (all zeros, integers in
+[0, 3]) and blocked cells (+inf), padded leading dimensions and the special upstream values.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2510_27351_amd as wf
+from paper_2510_27351_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+PREC = {torch.float32: "f32", torch.float64: "f64"}
+
+
+def oracle_grad(oracle_mod, C, gscore):
+    _, sel = oracle_mod.forward(C.numpy(), PREC[C.dtype], want_sel=True)
+    return oracle_mod.backward(sel, None, gscore, PREC[C.dtype])
+
+
+def run(C, gscore, source="ckpt", ckpt_k=64, g_C=None):
+    """(path adjoint, pipeline adjoint) on the device."""
+    Cd = C.to(DEV)
+    gs = None if gscore is None else torch.tensor(gscore, dtype=C.dtype, device=DEV)
+    m, n = C.shape
+    if source == "table":
+        D, _, _ = wf.forward(Cd)
+        kw = dict(D=D)
+    else:
+        _, _, ck = wf.forward(Cd, table=False, ckpt_k=ckpt_k)
+        kw = dict(ckpt=ck, ckpt_k=ckpt_k)
+    g = wf.backward(Cd, g_score=gs, g_C=g_C, **kw)
+    wf.select(Cd, **kw)
+    g2 = wf.reverse(m, n, C.dtype, g_score=gs)
+    torch.cuda.synchronize()
+    wf.last_async_error()
+    return g.cpu(), g2.cpu()
+
+
+def check(oracle_mod, C, gscore, label, **kw):
+    got, pipe = run(C, gscore, **kw)
+    want = oracle_grad(oracle_mod, C, 0.0 if gscore is None else gscore)
+    path_cells = int(np.count_nonzero(want))
+    print(f"{label}: {path_cells} path cells, bitwise vs oracle and pipeline", flush=True)
+    assert np.array_equal(got.numpy(), want), label
+    assert torch.equal(got, pipe), label
+
+
+SHAPES = [(1, 1), (1, 300), (300, 1), (2, 2), (64, 64), (65, 63), (127, 1025), (300, 200), (129, 4000)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_random_shapes(oracle_mod, shape, dtype):
+    m, n = shape
+    C = inputs.uniform(m, n, seed=7 * m + n, dtype=dtype)
+    check(oracle_mod, C, 1.0, f"{m}x{n} {dtype}")
+
+
+@pytest.mark.parametrize("source,k", [("table", 0), ("ckpt", 1), ("ckpt", 64), ("ckpt", 100)])
+def test_sources(oracle_mod, source, k):
+    C = inputs.normal_clipped(333, 1500, seed=21)
+    check(oracle_mod, C, -2.5, f"333x1500 {source} K={k}", source=source, ckpt_k=k or 64)
+
+
+@pytest.mark.parametrize("shape", [(2048, 3000), (4113, 1100), (1000, 1024)])
+def test_split_bands(oracle_mod, shape):
+    """Fewer than two bands per compute unit and n >= 1024: two column pieces per band (the
+    last band partial in the second case)."""
+    m, n = shape
+    for dtype in (torch.float32, torch.float64):
+        C = inputs.uniform(m, n, seed=m + 3 * n, dtype=dtype)
+        check(oracle_mod, C, 0.5, f"{m}x{n} {dtype} (split)")
+
+
+@pytest.mark.parametrize("shape", [(20000, 200), (70000, 6)])
+def test_many_bands(oracle_mod, shape):
+    m, n = shape
+    C = inputs.uniform(m, n, seed=m + n)
+    check(oracle_mod, C, 1.0, f"{m}x{n} ({(m + 63) // 64} bands)")
+
+
+@pytest.mark.parametrize("kind", ["zeros", "int03", "walls"])
+@pytest.mark.parametrize("shape", [(100, 90), (700, 1300), (2100, 1500)])
+def test_ties_and_blocked_cells(oracle_mod, kind, shape):
+    m, n = shape
+    if kind == "zeros":
+        C = torch.zeros(m, n)
+    elif kind == "int03":
+        C = torch.randint(0, 4, (m, n), generator=torch.Generator().manual_seed(m + n)).float()
+    else:
+        C = inputs.uniform(m, n, seed=m * n % 997)
+        C[m // 3, : (3 * n) // 4] = float("inf")   # a wall with a gap at the right
+        C[(2 * m) // 3, n // 5:] = float("inf")    # a wall with a gap at the left
+        C[:, n // 2][torch.arange(m) % 7 != 0] = float("inf")
+    for dtype in (torch.float32, torch.float64):
+        check(oracle_mod, C.to(dtype), 1.0, f"{m}x{n} {kind} {dtype}")
+
+
+def test_upstream_values_and_padding(oracle_mod):
+    C = inputs.uniform(500, 1200, seed=31)
+    for gs in (None, 0.0, -0.0, 3.0, -1e30):
+        check(oracle_mod, C, gs, f"gscore={gs}")
+    big = torch.full((500, 1207), float("nan"), device=DEV)
+    got, _ = run(C, 2.0, g_C=big[:, :1200])
+    assert torch.isnan(big[:, 1200:]).all()
+    assert np.array_equal(got.numpy(), oracle_grad(oracle_mod, C, 2.0))
+
+
+def test_repeat_and_reverse_after():
+    """Two calls in a row with different shapes reuse the stream's buffers; a wf_reverse
+    after a path adjoint runs on its selections."""
+    for m, n in ((3000, 2000), (700, 300), (3000, 2000)):
+        C = inputs.uniform(m, n, seed=m - n).to(DEV)
+        _, _, ck = wf.forward(C, table=False, ckpt_k=64)
+        gs = torch.tensor(1.0, device=DEV)
+        g = wf.backward(C, g_score=gs, ckpt=ck, ckpt_k=64)
+        g2 = wf.reverse(m, n, torch.float32, g_score=gs)
+        torch.cuda.synchronize()
+        assert torch.equal(g, g2)
