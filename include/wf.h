@@ -114,8 +114,18 @@ int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k);
  *   g_score     one element, or NULL for 0.
  *   g_D, ldgd   m x n upstream gradient of the table, or NULL for 0.
  *   g_C, ldgc   m x n output.
- * Uses (and grows) the device workspace: 4 bits per cell for the selections (three bit-planes
- * and padding) plus handoff words.  Results are bitwise reproducible; in float the sums
+ * With g_D given, the selections are recomputed and the reverse sweep runs band by band from
+ * the bottom up (wf_select then wf_reverse).  With g_D = NULL the adjoint is g_score on the
+ * cells of the argmin path traced back from cell (m-1, n-1) and exactly zero elsewhere (each
+ * value being 0 + g_score, the same in any summation order), and it is computed that way:
+ * the selection recompute also labels every cell with the exit of its path from its 64-row
+ * band, the labels of the bands' last rows are composed over groups of bands, and each band
+ * writes its part of the path (g_C is zeroed first, so g_score = NaN or +-inf reaches the
+ * path cells only).  The selections are left in the stream's workspace either way, so a
+ * wf_reverse may follow.
+ * Uses (and grows) the stream's workspace: 4 bits per cell for the selections (three
+ * bit-planes and padding), plus handoff words (g_D given) or one 32-bit exit per column of
+ * every band's last row (g_D = NULL).  Results are bitwise reproducible; in float the sums
  * round once per term in the order above.
  */
 int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* ckpt,
@@ -123,8 +133,9 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
                 int64_t ldgd, void* g_C, int64_t ldgc, void* stream);
 
 /*
- * The two halves of wf_backward, for callers that time or schedule them separately
- * (wf_backward is exactly wf_select followed by wf_reverse on the same stream).
+ * The two halves of the reverse pipeline, for callers that time or schedule them separately
+ * (wf_backward with g_D given is exactly wf_select followed by wf_reverse on the same stream;
+ * with g_D = NULL and a finite g_score wf_reverse gives the same g_C as wf_backward).
  * wf_select recomputes the predecessor selections of an m x n forward sweep (arguments as
  * for wf_backward) into the workspace of (current device, 'stream'); wf_reverse runs the
  * reverse sweep from them and writes g_C.  wf_reverse must be given the stream of its

@@ -156,6 +156,9 @@ class WfFunction(torch.autograd.Function):
     def forward(ctx, C: torch.Tensor, table: bool, ckpt_k: int):
         C = C.contiguous()
         ctx.table = table
+        # an output the loss does not use arrives as None, not as zeros: with the table's
+        # gradient absent the adjoint of the score is the argmin path (wf_backward)
+        ctx.set_materialize_grads(False)
         if C.dim() == 3:
             plan = _batch_plan(C)
             flat = C.view(-1)

@@ -128,3 +128,19 @@ def test_repeat_and_reverse_after():
         g2 = wf.reverse(m, n, torch.float32, g_score=gs)
         torch.cuda.synchronize()
         assert torch.equal(g, g2)
+
+
+def test_autograd_unused_outputs(oracle_mod):
+    """Through torch.autograd with the table returned: a loss of the score alone reaches the
+    argmin path (the table's gradient arrives as None, not as zeros); a loss of the table
+    alone gets the pipeline with no score term."""
+    C = inputs.uniform(300, 1100, seed=61)
+    Cd = C.to(DEV).requires_grad_(True)
+    D, score = wf.sweep(Cd, table=True)
+    (3.0 * score).backward()
+    assert np.array_equal(Cd.grad.cpu().numpy(), oracle_grad(oracle_mod, C, 3.0))
+    Cd.grad = None
+    D, score = wf.sweep(Cd, table=True)
+    W = inputs.uniform(300, 1100, seed=62).to(DEV)
+    (W * D).sum().backward()
+    assert torch.equal(Cd.grad, wf.backward(Cd.detach(), g_D=W, D=D.detach()))
