@@ -595,7 +595,7 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   if (rc != WF_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int nb = sa.nb;
-  const int32_t S = nb > 1 ? std::max<int32_t>(1, (int32_t)std::ceil(std::sqrt((double)(nb - 1)))) : 1;
+  const int32_t S = path_group_size(nb);
   const int32_t G = nb > 1 ? (nb - 1 + S - 1) / S : 0;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;

@@ -1379,15 +1379,17 @@ __device__ __forceinline__ int32_t path_resolve(const PathArgs& a, int b, int32_
 
 // F[g][p] for the groups g >= 1: the path entering the last band of group g at column p,
 // followed up through the group's bands.
-__global__ __launch_bounds__(256) void compose_kernel(PathArgs a) {
-  const int g = (int)blockIdx.y + 1;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n) return;
+__device__ __forceinline__ void compose_one(const PathArgs& a, int g, int64_t p) {
   const int lo = g * a.S;
   const int hi = (lo + a.S < a.nb - 1 ? lo + a.S : a.nb - 1) - 1;
   int32_t v = (int32_t)p;
   for (int b = hi; b >= lo && v >= 0; --b) v = path_resolve(a, b, a.exits[(int64_t)b * a.n + v]);
   a.F[(int64_t)g * a.n + p] = v;
+}
+
+__global__ __launch_bounds__(256) void compose_kernel(PathArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < a.n) compose_one(a, (int)blockIdx.y + 1, p);
 }
 
 // One wave per band: the column at which the path enters the band's last row (the last
@@ -1396,8 +1398,7 @@ __global__ __launch_bounds__(256) void compose_kernel(PathArgs a) {
 // selections, writing the score's upstream value on every cell of the path.  The rows'
 // runs of path cells are written by the lanes at once.
 template <typename T>
-__global__ __launch_bounds__(64) void walk_kernel(PathArgs a) {
-  const int b = (int)blockIdx.x;
+__device__ __forceinline__ void walk_band(const PathArgs& a, int b) {
   const int lane = (int)threadIdx.x;
   T gv = a.gscore ? *static_cast<const T*>(a.gscore) : T(0);
   gv = gv + T(0);  // the last cell's value is 0 + gscore
@@ -1461,6 +1462,94 @@ __global__ __launch_bounds__(64) void walk_kernel(PathArgs a) {
     }
     run_hi = col;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void walk_kernel(PathArgs a) {
+  walk_band<T>(a, (int)blockIdx.x);
+}
+
+// The path arguments of instance 'inst' of a batch (no split bands in a batch).
+template <typename T>
+__device__ __forceinline__ PathArgs inst_path(const BwdBatchArgs& b, const PathBufs& pb, const BwdInst& in, int inst) {
+  PathArgs a;
+  a.exits = pb.exits + in.sel_off / 8;
+  a.caps = pb.caps + in.sel_off / 4;
+  a.F = pb.F + in.sel_off / 8;
+  a.sel = b.sel + in.sel_off;
+  a.gscore = b.gscores ? static_cast<const T*>(b.gscores) + inst : nullptr;
+  a.gC = static_cast<T*>(b.gC) + in.off;
+  a.ldgc = in.n;
+  a.m = in.m;
+  a.n = in.n;
+  a.split = 0;
+  a.nb = in.nb;
+  a.Ks = (int32_t)((in.n + kBand - 1 + kSub - 1) / kSub);
+  a.S = path_group_size(in.nb);
+  a.G = in.nb > 1 ? (in.nb - 1 + a.S - 1) / a.S : 0;
+  return a;
+}
+
+// Batched labelled selection recompute: sel_batch_kernel with every instance's exits and
+// captured labels, and its gradient zeroed.
+template <typename T>
+__global__ __launch_bounds__(128, 1) void sel_path_batch_kernel(BwdBatchArgs b, PathBufs pb) {
+  __shared__ SelLds<T> L;
+  __shared__ SelShared sh;
+  Control* ctl = b.ctl;
+  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) sh.abort = 0u;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      sh.loaded = 0u;
+      sh.steps = 0u;
+    }
+    claim_next(ctl, &sh.item, &sh.abort);
+    const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.item);
+    if (item >= (uint32_t)b.n_items || sh.abort != 0u) break;
+    const BatchItem it = load_uniform(b.items + item);
+    const BwdInst in = load_uniform(b.inst + it.inst);
+    SelArgs a;
+    a.C = static_cast<const T*>(b.C) + in.off;
+    if (b.ckpt_k > 0) {
+      a.top = static_cast<const T*>(b.top) + in.ck_off;
+      a.ld_top = in.n;
+    } else {
+      a.top = static_cast<const T*>(b.top) + in.off + 63 * in.n;
+      a.ld_top = 64 * in.n;
+    }
+    a.ldc = in.n;
+    a.m = in.m;
+    a.n = in.n;
+    a.nb = in.nb;
+    a.sel = b.sel + in.sel_off;
+    a.ctl = ctl;
+    a.split = 0;
+    a.left = nullptr;
+    a.ld_left = 0;
+    const PathLabels po{pb.exits + in.sel_off / 8, pb.caps + in.sel_off / 4, static_cast<T*>(b.gC) + in.off, in.n};
+    sel_item<T, true>(L, sh, a, it.band, 0, po);
+    __syncthreads();
+  }
+  finish_launch(ctl, epoch);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void compose_batch_kernel(BwdBatchArgs b, PathBufs pb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int i = (int)blockIdx.y; i < pb.batch; i += (int)gridDim.y) {
+    const BwdInst in = b.inst[i];
+    const PathArgs a = inst_path<T>(b, pb, in, i);
+    if (a.G < 2 || t >= (int64_t)(a.G - 1) * a.n) continue;
+    compose_one(a, 1 + (int)(t / a.n), t % a.n);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void walk_batch_kernel(BwdBatchArgs b, PathBufs pb) {
+  const BatchItem it = load_uniform(b.items + blockIdx.x);
+  const BwdInst in = load_uniform(b.inst + it.inst);
+  walk_band<T>(inst_path<T>(b, pb, in, it.inst), it.band);
 }
 
 template <typename T, bool TRACE>
@@ -1531,6 +1620,30 @@ hipError_t launch_path(int dtype, const PathArgs& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_path_batch_t(const BwdBatchArgs& b, const PathBufs& pb, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((sel_path_batch_kernel<T>), dim3(grid), dim3(128), 0, s, b, pb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (pb.max_cols > 0) {
+    const unsigned gy = (unsigned)std::min<int32_t>(pb.batch, 65535);
+    hipLaunchKernelGGL((compose_batch_kernel<T>), dim3((unsigned)((pb.max_cols + 255) / 256), gy), dim3(256), 0, s, b,
+                       pb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((walk_batch_kernel<T>), dim3((unsigned)b.n_items), dim3(64), 0, s, b, pb);
+  return hipGetLastError();
+}
+
+hipError_t launch_path_batch(int dtype, const BwdBatchArgs& b, const PathBufs& pb, int grid, hipStream_t s) {
+  switch (dtype) {
+    case 0: return launch_path_batch_t<float>(b, pb, grid, s);
+    case 1: return launch_path_batch_t<double>(b, pb, grid, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_select_batch(int dtype, const BwdBatchArgs& b, int grid, hipStream_t s) {

@@ -51,9 +51,32 @@ struct PathArgs {
   int32_t nb, Ks, S, G;
 };
 
+// Bands per group of the composition: the smallest S with S * S >= nb - 1.
+__host__ __device__ inline int32_t path_group_size(int32_t nb) {
+  int32_t s = 1;
+  while ((int64_t)s * s < (int64_t)nb - 1) ++s;
+  return s;
+}
+
+// Buffers of the batched path adjoint (a plan's): instance i's exits at word sel_off / 8 of
+// 'exits', its captured labels at sel_off / 4 of 'caps' and its group maps at sel_off / 8 of
+// 'F' (sel_off: the instance's offset in the selection buffer, whose nb * Ks * 512 words per
+// instance bound all three).
+struct PathBufs {
+  int32_t* exits;
+  int32_t* caps;
+  int32_t* F;
+  int32_t batch;
+  int32_t pad;
+  int64_t max_cols;  // the largest (G - 1) * n over the instances
+};
+
 // Defined in wf_bwd.hip, float (dtype 0) and double (dtype 1).
 hipError_t launch_select_path(int dtype, const SelArgs& a, const PathLabels& p, int grid, hipStream_t s);
 hipError_t launch_zero(int dtype, void* p, int64_t m, int64_t n, int64_t ld, int grid, hipStream_t s);
 hipError_t launch_path(int dtype, const PathArgs& a, hipStream_t s);
+// The batch: labelled selection recompute (which also zeroes every instance's gradient),
+// composition and walk over the plan's (instance, band) work list.
+hipError_t launch_path_batch(int dtype, const BwdBatchArgs& b, const PathBufs& pb, int grid, hipStream_t s);
 
 }  // namespace wf

@@ -16,6 +16,7 @@
 #include "../../include/wf.h"
 #include "wf_host.h"
 #include "wf_internal.h"
+#include "wf_path.h"
 
 using namespace wf;
 
@@ -46,6 +47,11 @@ struct wf_plan {
   int32_t b_k = -1;               // K of b_inst's checkpoint offsets (-1: not built)
   uint32_t* b_sel = nullptr;      // selection bit-planes of every instance
   uint64_t* b_bnd = nullptr;      // reverse handoff words of every instance
+  // the adjoint of the scores alone (no g_D): exits, captured labels, group maps
+  int32_t* b_exits = nullptr;
+  int32_t* b_caps = nullptr;
+  int32_t* b_F = nullptr;
+  int64_t b_max_cols = 0;         // the largest (G - 1) * n over the instances
 };
 
 namespace {
@@ -272,6 +278,9 @@ void free_plan(wf_plan* p) {
   if (p->b_inst) (void)hipFree(p->b_inst);
   if (p->b_items) (void)hipFree(p->b_items);
   if (p->b_sel) (void)hipFree(p->b_sel);
+  if (p->b_exits) (void)hipFree(p->b_exits);
+  if (p->b_caps) (void)hipFree(p->b_caps);
+  if (p->b_F) (void)hipFree(p->b_F);
   if (p->b_bnd) (void)hipFree(p->b_bnd);
   free_control(p->ctl);
   delete p;
@@ -301,6 +310,9 @@ int ensure_bwd(wf_plan& p, int32_t K) {
     b.bnd_off = bnd_words;
     const int64_t Ks = (p.n[i] + kBand - 1 + 63) / 64;
     sel_words += (int64_t)b.nb * Ks * 64 * 8;
+    const int32_t S = path_group_size(b.nb);
+    const int64_t G = b.nb > 1 ? (b.nb - 1 + S - 1) / S : 0;
+    p.b_max_cols = std::max<int64_t>(p.b_max_cols, (G > 1 ? G - 1 : 0) * p.n[i]);
     bnd_words += (int64_t)(b.nb - 1) * p.n[i] * 2 * W;
     max_nb = std::max(max_nb, b.nb);
   }
@@ -329,6 +341,19 @@ int ensure_bwd(wf_plan& p, int32_t K) {
       return WF_E_DEVICE;
     p.b_n_items = (int32_t)items.size();
     if (hipMalloc(&p.b_sel, (size_t)sel_words * sizeof(uint32_t)) != hipSuccess) { p.b_sel = nullptr; return WF_E_NOMEM; }
+    // the path adjoint's buffers, addressed from each instance's selection offset
+    if (hipMalloc(&p.b_exits, (size_t)(sel_words / 8) * sizeof(int32_t)) != hipSuccess) {
+      p.b_exits = nullptr;
+      return WF_E_NOMEM;
+    }
+    if (hipMalloc(&p.b_caps, (size_t)(sel_words / 4) * sizeof(int32_t)) != hipSuccess) {
+      p.b_caps = nullptr;
+      return WF_E_NOMEM;
+    }
+    if (hipMalloc(&p.b_F, (size_t)(sel_words / 8) * sizeof(int32_t)) != hipSuccess) {
+      p.b_F = nullptr;
+      return WF_E_NOMEM;
+    }
     const size_t bw = (size_t)std::max<int64_t>(bnd_words, 1);
     if (hipMalloc(&p.b_bnd, bw * sizeof(uint64_t)) != hipSuccess) { p.b_bnd = nullptr; return WF_E_NOMEM; }
     // tag 0 never equals a launch epoch, so zeroed words read as "not yet written"
@@ -587,6 +612,14 @@ int wf_batch_backward(wf_plan* plan, const void* C, const void* ckpt, int32_t ck
   b.sel = plan->b_sel;
   b.bnd = plan->b_bnd;
   b.ctl = plan->ctl;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!g_D) {
+    // the scores alone: each instance's upstream value on its argmin path, zero elsewhere
+    const PathBufs pb{plan->b_exits, plan->b_caps, plan->b_F, plan->batch, 0, plan->b_max_cols};
+    return launch_path_batch(plan->dtype, b, pb, std::min(b.n_items, 2 * plan->num_cus), st) == hipSuccess
+               ? WF_OK
+               : WF_E_DEVICE;
+  }
   // the reverse tile of the batch's largest instance
   int32_t big = 0;
   for (int32_t i = 1; i < plan->batch; ++i)

@@ -144,3 +144,46 @@ def test_autograd_unused_outputs(oracle_mod):
     W = inputs.uniform(300, 1100, seed=62).to(DEV)
     (W * D).sum().backward()
     assert torch.equal(Cd.grad, wf.backward(Cd.detach(), g_D=W, D=D.detach()))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("source,ckpt_k", [("table", 0), ("ckpt", 64), ("ckpt", 100)])
+def test_batch_scores_alone(oracle_mod, dtype, source, ckpt_k):
+    """wf_batch_backward with no g_D takes the path method per instance (labelled batched
+    recompute, which zeroes every instance's gradient, composition, one wave per (instance,
+    band) walking): every instance bitwise equal to the oracle's adjoint and to the batched
+    pipeline (zero g_D), ragged shapes with one-cell/row/column instances and up to 33 bands,
+    the gaps between caller offsets untouched."""
+    g = torch.Generator().manual_seed(71)
+    ms = [1, 1, 200, 64, 65, 2100, 700, 130] + torch.randint(1, 400, (8,), generator=g).tolist()
+    ns = [1, 257, 1, 64, 63, 90, 1300, 2000] + torch.randint(1, 400, (8,), generator=g).tolist()
+    offsets, at = [], 5
+    for m, n in zip(ms, ns):
+        offsets.append(at)
+        at += m * n + 37
+    plan = wf.Plan(ms, ns, dtype=dtype, offsets=offsets, tile=64, rows=1)
+    mats = [torch.rand(m, n, generator=g, dtype=dtype) for m, n in zip(ms, ns)]
+    C = torch.full((plan.elems,), 9.0, dtype=dtype, device=DEV)
+    for o, x in zip(plan.offsets, mats):
+        C[o:o + x.numel()] = x.reshape(-1).to(DEV)
+    gs = (torch.rand(len(ms), generator=g, dtype=dtype) * 4 - 2).to(DEV)
+    if source == "table":
+        _, D, _ = plan.forward_ckpt(C, 0, table=True)
+        kw = dict(D=D)
+    else:
+        _, _, ck = plan.forward_ckpt(C, ckpt_k)
+        kw = dict(ckpt=ck, ckpt_k=ckpt_k)
+    gC = torch.full((plan.elems,), float("nan"), dtype=dtype, device=DEV)
+    got = plan.backward(C, g_scores=gs, g_C=gC, **kw)
+    pipe = plan.backward(C, g_scores=gs, g_D=torch.zeros_like(C), **kw)
+    torch.cuda.synchronize()
+    wf.last_async_error()
+    inside = torch.zeros(plan.elems, dtype=torch.bool, device=DEV)
+    for o, m, n in zip(plan.offsets, ms, ns):
+        inside[o:o + m * n] = True
+    assert torch.isnan(gC[~inside]).all()
+    for i, (o, m, n) in enumerate(zip(plan.offsets, ms, ns)):
+        want = oracle_grad(oracle_mod, mats[i], float(gs[i]))
+        a = got[o:o + m * n].view(m, n).cpu().numpy()
+        assert np.array_equal(a, want), (i, m, n)
+        assert torch.equal(got[o:o + m * n], pipe[o:o + m * n]), (i, m, n)
