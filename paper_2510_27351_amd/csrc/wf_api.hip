@@ -468,30 +468,41 @@ int prepare_select(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, 
     sa.top = static_cast<const char*>(D) + (size_t)63 * ldd * es;
     sa.ld_top = 64 * ldd;
   }
-  // With fewer than two bands per CU, each band is swept as two column pieces (two
-  // workgroups per CU), the second starting from a column of the forward table that the
-  // source holds: a block column of the checkpoint grid (a multiple of K) or any column of
-  // the saved table; the split is a multiple of 64 near n/2.
+  // With fewer bands than the CUs' workgroup slots (two per CU: a workgroup's ring takes
+  // half of the LDS), each band is swept as up to four column pieces, each but the first
+  // starting from a column of the forward table that the source holds: a block column of the
+  // checkpoint grid (a multiple of K) or any column of the saved table.  The pieces are w
+  // columns wide (a multiple of lcm(K, 64)), the last one the rest, every piece at least 256
+  // columns.
+  const int64_t per_cu = 2;
   sa.split = 0;
   sa.left = nullptr;
   sa.ld_left = 0;
-  if (nb < 2 * (int64_t)ws->num_cus && n >= 1024) {
+  sa.left_pstride = 0;
+  sa.pieces = 1;
+  sa.pad = 0;
+  {
     const int64_t K = ckpt_k > 0 ? ckpt_k : 64;
     const int64_t L = K / std::gcd<int64_t>(K, 64) * 64;  // lcm(K, 64)
-    const int64_t c = (n / 2 + L / 2) / L * L;
-    if (c >= 256 && c <= n - 256) {
-      sa.split = c;
-      if (ckpt_k > 0) {  // block column q = c/K holds D[.][c-1]
-        sa.left = static_cast<const char*>(ckpt) + ((size_t)(nb - 1) * n + (size_t)(c / K - 1) * m) * es;
+    for (int64_t P = std::min<int64_t>(kMaxPieces, per_cu * ws->num_cus / nb); P >= 2; --P) {
+      const int64_t w = (n / P + L / 2) / L * L;
+      if (w < 256 || n - (P - 1) * w < 256) continue;
+      sa.split = w;
+      sa.pieces = (int32_t)P;
+      if (ckpt_k > 0) {  // block column q = w/K holds D[.][w-1]
+        sa.left = static_cast<const char*>(ckpt) + ((size_t)(nb - 1) * n + (size_t)(w / K - 1) * m) * es;
         sa.ld_left = 1;
+        sa.left_pstride = (w / K) * m;
       } else {
-        sa.left = static_cast<const char*>(D) + (size_t)(c - 1) * es;
+        sa.left = static_cast<const char*>(D) + (size_t)(w - 1) * es;
         sa.ld_left = ldd;
+        sa.left_pstride = w;
       }
+      break;
     }
   }
-  const int64_t items = sa.split > 0 ? 2 * nb : nb;
-  const int grid = (int)std::min<int64_t>(items, (sa.split > 0 ? 2 : 1) * (int64_t)ws->num_cus);
+  const int64_t items = nb * sa.pieces;
+  const int grid = (int)std::min<int64_t>(items, per_cu * (int64_t)ws->num_cus);
   sa.m = m;
   sa.n = n;
   sa.nb = (int32_t)nb;
@@ -600,7 +611,7 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
   PathWs* pw = nullptr;
-  rc = ensure_path(dev, st, (size_t)nb * (size_t)n, (size_t)nb * 2 * 64, (size_t)G * (size_t)n, &pw);
+  rc = ensure_path(dev, st, (size_t)nb * (size_t)n, (size_t)nb * kMaxPieces * 64, (size_t)G * (size_t)n, &pw);
   if (rc != WF_OK) return rc;
   // The gradient is zeroed by the sweep itself for float32 (its zero stores cost the sweep
   // less than a pass of their own) and by a pass of its own before it for float64 (twice the
@@ -622,6 +633,8 @@ int wf_backward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, con
   pa.m = m;
   pa.n = n;
   pa.split = sa.split;
+  pa.pieces = sa.pieces;
+  pa.pad = 0;
   pa.nb = nb;
   pa.Ks = (int32_t)((n + kBand - 1 + 63) / 64);
   pa.S = S;

@@ -72,6 +72,19 @@ struct BCfg {
   static constexpr int NSUB = RING / kSub;  // 64-slot sub-chunks in a ring
 };
 
+// LDS ring of the selection recompute: 256 slots per row for 4-byte elements, 128 for 8-byte
+// ones (two workgroups per CU either way).  A 128-slot ring for 4-byte elements lets four
+// workgroups share a CU, but four compute waves per CU swept a band's pieces no faster in
+// total than two (measured on MI355X), and the smaller ring stalled the plain recompute on
+// its loader.  The row pitch keeps the 64 rows' 16-byte accesses conflict-free.
+template <typename T>
+struct SCfg {
+  using E = Elem<T>;
+  static constexpr int RING = sizeof(T) == 4 ? 256 : 128;
+  static constexpr int PITCH = RING + 16 / (int)sizeof(T);
+  static constexpr int MASK = RING - 1;
+};
+
 // Layout of the selection bit-planes in global memory: for band b, sub-chunk k (slots
 // [64k, 64k+64)) and lane r, eight words: W[0..1], N[0..1], NW[0..1], 0, 0 -- bit j of word
 // h of a plane is slot 64k + 32h + j of row r.
@@ -119,23 +132,25 @@ struct SelGroup {
 template <typename T>
 __device__ __forceinline__ void sel_load_group(const T* __restrict__ S, const T* __restrict__ Tr, int slot, int lane,
                                                SelGroup<T>& r) {
-  using C = BCfg<T>;
+  using C = SCfg<T>;
   r.c = *reinterpret_cast<const Vec4<T>*>(S + lane * C::PITCH + slot);
   r.t = *reinterpret_cast<const Vec4<T>*>(Tr + slot);
 }
 
-// Sub-chunks [k0, k1) of the band that one piece of it sweeps: the whole band, or with a
-// column split at c = split (a multiple of 64) sub-chunks [0, c/64] for columns below c and
-// [c/64, Ks) for the rest.  Sub-chunk c/64 is swept by both; only the first stores it (its
-// cells of columns >= c are plain cells of the first piece's sweep too).
+// Sub-chunks [k0, k1) of the band that one piece of it sweeps: the whole band, or with
+// column splits every w = split columns (a multiple of 64) sub-chunks [p w/64, (p+1) w/64]
+// for piece p and [p w/64, Ks) for the last.  Sub-chunk (p+1) w/64 is swept by pieces p
+// and p+1; only piece p stores it (its cells of columns >= (p+1) w are plain cells of piece
+// p's sweep too).
 struct SelPiece {
   int k0, k1;
-  bool second;
+  bool second;  // piece >= 1: enters from column k0 * 64 - 1
+  int piece;
 };
 __device__ __forceinline__ SelPiece sel_piece(const SelArgs& a, int piece, int Ks) {
   const int ks = (int)(a.split / kSub);
-  if (a.split == 0) return {0, Ks, false};
-  return piece == 0 ? SelPiece{0, ks + 1, false} : SelPiece{ks, Ks, true};
+  if (a.split == 0) return {0, Ks, false, 0};
+  return SelPiece{piece * ks, piece == a.pieces - 1 ? Ks : (piece + 1) * ks + 1, piece > 0, piece};
 }
 
 // One sub-chunk of the compute wave (see sel_compute); ENTRY: the first sub-chunk of a
@@ -148,8 +163,12 @@ constexpr int kZeroAux = 2;
 // 0) and its step, lane 63's labels of the sub-chunk shifted in one per step, and the label
 // captured at slot cbase + lane (CAP sub-chunks).
 struct LabState {
-  int32_t LX, LNW, tcol, inc, acc, cap, cbase;
+  int32_t LX, LNW, tcol, inc, acc, cap, cbase, entry;
 };
+
+// The label a split band's piece p >= 1 gives row r at its entry column: the label of
+// (r, entry column) in piece p - 1, which that piece captures (caps slot (p - 1) * 64 + r).
+__device__ __forceinline__ int32_t sym_label(int piece, int r) { return -2 - ((piece - 1) * 64 + r); }
 
 // Selection bits and the label of one cell: N if N < NW, W if W < min(N, NW), else NW.
 __device__ __forceinline__ void sel_bits_lab(uint32_t& pn, uint32_t& pw, float N, float NW, float X, float m,
@@ -177,7 +196,7 @@ template <typename T, bool ENTRY, bool LAB = false, bool CAP = false>
 __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __restrict__ Tr, const SelArgs& a, int band,
                                         int Ks, int k, int rows, int64_t n, T& X, T& NW, T left,
                                         SelGroup<T> (&P)[2], LabState& ls, const PathLabels& po) {
-  using C = BCfg<T>;
+  using C = SCfg<T>;
   using E = typename C::E;
   typedef int v4i __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
@@ -233,7 +252,7 @@ __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __rest
       NW = N;
       if (ENTRY && 4 * g + q == lane - 1) {
         X = left;
-        if constexpr (LAB) ls.LX = -2 - lane;
+        if constexpr (LAB) ls.LX = ls.entry - lane;
       }
     }
 
@@ -312,7 +331,7 @@ __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __rest
 template <typename T, bool LAB>
 __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __restrict__ Tr, SelShared& sh,
                                             const SelArgs& a, int band, int Ks, SelPiece pc, const PathLabels& po) {
-  using C = BCfg<T>;
+  using C = SCfg<T>;
   using E = typename C::E;
   const int lane = threadIdx.x & 63;
   const int64_t n = opaque(a.n);
@@ -321,8 +340,8 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
   T NW = (lane == 0 && band == 0) ? E::zero() : E::inf();  // virtual corner D[-1][-1] = 0
   T left = E::inf();
   if (pc.second) {
-    const T* lp = static_cast<const T*>(a.left);
-    const int64_t c = opaque(a.split) - 1;
+    const T* lp = static_cast<const T*>(a.left) + (int64_t)(pc.piece - 1) * a.left_pstride;
+    const int64_t c = opaque(a.split) * pc.piece - 1;
     if (lane < rows) left = lp[((int64_t)band * kBand + lane) * a.ld_left];
     if (lane == 0) {
       X = left;
@@ -334,17 +353,18 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
   LabState ls;
   bool has_cap = false;
   if constexpr (LAB) {
-    const int64_t c0 = pc.second ? opaque(a.split) : 0;
+    const int64_t c0 = pc.second ? opaque(a.split) * pc.piece : 0;
     ls.inc = band > 0 ? 1 : 0;
     ls.tcol = band > 0 ? (int32_t)c0 : -1;
-    ls.LX = (pc.second && lane == 0) ? -2 : -1;
+    ls.LX = (pc.second && lane == 0) ? sym_label(pc.piece, 0) : -1;
     ls.LNW = (pc.second && lane == 0 && band > 0) ? (int32_t)(c0 - 1) : -1;
     ls.acc = 0;
     ls.cap = -1;
     ls.cbase = 0;
-    if (a.split > 0 && !pc.second) {
+    ls.entry = pc.second ? sym_label(pc.piece, 0) : 0;
+    if (a.split > 0 && pc.piece < a.pieces - 1) {
       has_cap = true;
-      ls.cbase = (int32_t)(a.split - 1);
+      ls.cbase = (int32_t)(a.split * (pc.piece + 1) - 1);
     } else if (band == a.nb - 1) {
       has_cap = true;
       ls.cbase = (int32_t)(n - 1);
@@ -376,7 +396,7 @@ __device__ __forceinline__ void sel_compute(const T* __restrict__ S, const T* __
     lds_signal(&sh.steps, (uint32_t)(kSub * (kl + 1)));
   }
   if constexpr (LAB) {
-    if (has_cap) po.caps[((int64_t)band * 2 + (pc.second ? 1 : 0)) * 64 + lane] = ls.cap;
+    if (has_cap) po.caps[((int64_t)band * kMaxPieces + pc.piece) * 64 + lane] = ls.cap;
   }
 }
 
@@ -418,7 +438,7 @@ __device__ __forceinline__ void sel_load_sub(Vec4<T> (&x)[16], T& tv, __amdgpu_b
 template <typename T>
 __device__ __forceinline__ void sel_store_sub(T* S, T* Tr, const Vec4<T> (&x)[16], T tv, bool has_top, int k,
                                               int rows, int64_t n) {
-  using C = BCfg<T>;
+  using C = SCfg<T>;
   using E = typename C::E;
   const int lane = threadIdx.x & 63;
   const bool interior = rows == kBand && k > 0 && (int64_t)kSub * k + kSub <= n;
@@ -441,7 +461,7 @@ __device__ __forceinline__ void sel_store_sub(T* S, T* Tr, const Vec4<T> (&x)[16
 template <typename T>
 __device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const SelArgs& a, int band, int Ks,
                                            SelPiece pc) {
-  using C = BCfg<T>;
+  using C = SCfg<T>;
   constexpr int PF = SelPF<T>::PF;
   const int64_t ldc = opaque(a.ldc), n = opaque(a.n), m = opaque(a.m);
   const int64_t row0 = (int64_t)band * kBand;
@@ -491,8 +511,8 @@ __device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const Sel
 
 template <typename T>
 struct SelLds {
-  Vec4<T> S4[kBand * BCfg<T>::PITCH / 4];
-  Vec4<T> Tr4[BCfg<T>::RING / 4];
+  Vec4<T> S4[kBand * SCfg<T>::PITCH / 4];
+  Vec4<T> Tr4[SCfg<T>::RING / 4];
 };
 
 // One work item: band 'band' (piece 'piece' of it when the band is split) of the instance
@@ -524,7 +544,7 @@ __global__ __launch_bounds__(128, 1) void sel_kernel(SelArgs a) {
     }
     claim_next(ctl, &sh.item, &sh.abort);
     // work items: bands, or (band, piece) pairs of split bands
-    const int pieces = a.split > 0 ? 2 : 1;
+    const int pieces = a.split > 0 ? a.pieces : 1;
     const int item = (int)sh.item;
     if (item >= a.nb * pieces || sh.abort != 0u) break;
     sel_item<T>(L, sh, a, item / pieces, item % pieces);
@@ -571,6 +591,9 @@ __global__ __launch_bounds__(128, 1) void sel_batch_kernel(BwdBatchArgs b) {
     a.split = 0;
     a.left = nullptr;
     a.ld_left = 0;
+    a.left_pstride = 0;
+    a.pieces = 1;
+    a.pad = 0;
     sel_item<T>(L, sh, a, it.band, 0);
     __syncthreads();
   }
@@ -1344,7 +1367,7 @@ __global__ __launch_bounds__(128, 1) void sel_path_kernel(SelArgs a, PathLabels 
       sh.steps = 0u;
     }
     claim_next(ctl, &sh.item, &sh.abort);
-    const int pieces = a.split > 0 ? 2 : 1;
+    const int pieces = a.split > 0 ? a.pieces : 1;
     const int item = (int)sh.item;
     if (item >= a.nb * pieces || sh.abort != 0u) break;
     sel_item<T, true>(L, sh, a, item / pieces, item % pieces, po);
@@ -1373,7 +1396,10 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ p, int64_t m,
 // An exit as stored (a column, -1, or -2 - r of a split band's second piece) made a column
 // or -1; anything out of range reads as -1.
 __device__ __forceinline__ int32_t path_resolve(const PathArgs& a, int b, int32_t v) {
-  if (v <= -2) v = v >= -65 ? a.caps[(int64_t)b * 2 * 64 + (-2 - v)] : -1;
+  // a label of piece p >= 1 names a row of piece p - 1's capture, which may name one of
+  // piece p - 2's, and so on
+  for (int hop = 0; hop < kMaxPieces && v <= -2; ++hop)
+    v = v >= -1 - 64 * (kMaxPieces - 1) ? a.caps[(int64_t)b * kMaxPieces * 64 + (-2 - v)] : -1;
   return (v >= 0 && v < a.n) ? v : -1;
 }
 
@@ -1408,8 +1434,8 @@ __device__ __forceinline__ void walk_band(const PathArgs& a, int b) {
   const int rows_last = (int)(a.m - (int64_t)(nb - 1) * kBand);
   int32_t q = (int32_t)(n - 1);
   if (b < nb - 1) {
-    const int endp = a.split > 0 ? 1 : 0;
-    q = path_resolve(a, nb - 1, a.caps[((int64_t)(nb - 1) * 2 + endp) * 64 + rows_last - 1]);
+    const int endp = a.split > 0 ? a.pieces - 1 : 0;
+    q = path_resolve(a, nb - 1, a.caps[((int64_t)(nb - 1) * kMaxPieces + endp) * 64 + rows_last - 1]);
     const int gb = b / a.S;
     for (int g = (nb - 2) / a.S; g > gb && q >= 0; --g) {
       q = a.F[(int64_t)g * n + q];
@@ -1474,7 +1500,7 @@ template <typename T>
 __device__ __forceinline__ PathArgs inst_path(const BwdBatchArgs& b, const PathBufs& pb, const BwdInst& in, int inst) {
   PathArgs a;
   a.exits = pb.exits + in.sel_off / 8;
-  a.caps = pb.caps + in.sel_off / 4;
+  a.caps = pb.caps + in.sel_off / 2;
   a.F = pb.F + in.sel_off / 8;
   a.sel = b.sel + in.sel_off;
   a.gscore = b.gscores ? static_cast<const T*>(b.gscores) + inst : nullptr;
@@ -1483,6 +1509,7 @@ __device__ __forceinline__ PathArgs inst_path(const BwdBatchArgs& b, const PathB
   a.m = in.m;
   a.n = in.n;
   a.split = 0;
+  a.pieces = 1;
   a.nb = in.nb;
   a.Ks = (int32_t)((in.n + kBand - 1 + kSub - 1) / kSub);
   a.S = path_group_size(in.nb);
@@ -1527,7 +1554,10 @@ __global__ __launch_bounds__(128, 1) void sel_path_batch_kernel(BwdBatchArgs b, 
     a.split = 0;
     a.left = nullptr;
     a.ld_left = 0;
-    const PathLabels po{pb.exits + in.sel_off / 8, pb.caps + in.sel_off / 4, static_cast<T*>(b.gC) + in.off, in.n};
+    a.left_pstride = 0;
+    a.pieces = 1;
+    a.pad = 0;
+    const PathLabels po{pb.exits + in.sel_off / 8, pb.caps + in.sel_off / 2, static_cast<T*>(b.gC) + in.off, in.n};
     sel_item<T, true>(L, sh, a, it.band, 0, po);
     __syncthreads();
   }

@@ -76,12 +76,16 @@ struct SelArgs {
   int32_t nb;         // 64-row bands
   uint32_t* sel;
   Control* ctl;
-  // Column split (split > 0): each band is swept as two pieces, columns [0, split) and
-  // [split, n), split a multiple of 64; the second starts from column split-1 of the forward
-  // table, D[i][split-1] at left + i * ld_left.
+  // Column split (split > 0): each band is swept as 'pieces' pieces, columns
+  // [p * split, (p + 1) * split) and the last one to n, split a multiple of 64; piece p >= 1
+  // starts from column p * split - 1 of the forward table, D[i][p * split - 1] at
+  // left + (p - 1) * left_pstride + i * ld_left (elements).
   int64_t split;
   const void* left;
   int64_t ld_left;
+  int64_t left_pstride;
+  int32_t pieces;
+  int32_t pad;
 };
 
 // Arguments of the reverse adjoint sweep (second half): bands of 64 rows from the bottom

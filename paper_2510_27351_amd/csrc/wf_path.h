@@ -20,15 +20,17 @@ namespace wf {
 
 // Outputs of the labelled selection recompute.
 //   exits  nb * n words: exits[b * n + p] is the exit of the path from cell (last row of
-//          band b, column p), b < nb - 1; -1 if the path leaves the matrix; -2 - r if the
-//          band is split and the path leaves the second piece through row r of column
-//          split - 1 (resolved by caps).
-//   caps   nb * 2 * 64 words: caps[(b * 2 + piece) * 64 + r] = the exit of cell (r, c) of
-//          band b, with c = split - 1 for the first piece of a split band and c = n - 1 for
-//          the piece of the last band that holds column n - 1.
+//          band b, column p), b < nb - 1; -1 if the path leaves the matrix; for a split band
+//          -2 - ((q - 1) * 64 + r) if the path leaves piece q >= 1 through row r of its entry
+//          column q * split - 1 (resolved by caps, possibly through several pieces).
+//   caps   nb * kMaxPieces * 64 words: caps[(b * kMaxPieces + q) * 64 + r] = the label of
+//          cell (r, c) of band b, with c = (q + 1) * split - 1 for a piece q that another
+//          follows and c = n - 1 for the piece of the last band that holds column n - 1.
 //   gC, ldgc  the gradient to zero in the same sweep (its compute wave stores zeros over
 //          columns [64k, 64k + 64) of the band's rows after every sub-chunk k it sweeps), or
 //          null when a pass of its own zeroes it.
+constexpr int kMaxPieces = 4;  // column pieces a band's selection recompute is split into
+
 struct PathLabels {
   int32_t* exits;
   int32_t* caps;
@@ -49,6 +51,7 @@ struct PathArgs {
   int64_t ldgc;
   int64_t m, n, split;
   int32_t nb, Ks, S, G;
+  int32_t pieces, pad;
 };
 
 // Bands per group of the composition: the smallest S with S * S >= nb - 1.
@@ -59,7 +62,7 @@ __host__ __device__ inline int32_t path_group_size(int32_t nb) {
 }
 
 // Buffers of the batched path adjoint (a plan's): instance i's exits at word sel_off / 8 of
-// 'exits', its captured labels at sel_off / 4 of 'caps' and its group maps at sel_off / 8 of
+// 'exits', its captured labels at sel_off / 2 of 'caps' and its group maps at sel_off / 8 of
 // 'F' (sel_off: the instance's offset in the selection buffer, whose nb * Ks * 512 words per
 // instance bound all three).
 struct PathBufs {

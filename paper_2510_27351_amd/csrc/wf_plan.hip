@@ -346,7 +346,7 @@ int ensure_bwd(wf_plan& p, int32_t K) {
       p.b_exits = nullptr;
       return WF_E_NOMEM;
     }
-    if (hipMalloc(&p.b_caps, (size_t)(sel_words / 4) * sizeof(int32_t)) != hipSuccess) {
+    if (hipMalloc(&p.b_caps, (size_t)(sel_words / 2) * sizeof(int32_t)) != hipSuccess) {
       p.b_caps = nullptr;
       return WF_E_NOMEM;
     }

@@ -73,10 +73,12 @@ def test_sources(oracle_mod, source, k):
     check(oracle_mod, C, -2.5, f"333x1500 {source} K={k}", source=source, ckpt_k=k or 64)
 
 
-@pytest.mark.parametrize("shape", [(2048, 3000), (4113, 1100), (1000, 1024)])
+@pytest.mark.parametrize("shape", [(2048, 3000), (4113, 1100), (1000, 1024), (9600, 1100), (12800, 1100)])
 def test_split_bands(oracle_mod, shape):
-    """Fewer than two bands per compute unit and n >= 1024: two column pieces per band (the
-    last band partial in the second case)."""
+    """Fewer bands than the compute units' workgroup slots: up to four column pieces per
+    band (four for the first three shapes, three for 150 bands, two for 200), whose pieces'
+    exits name rows of the previous piece's entry column, resolved through up to three
+    pieces (the last band partial in the second case)."""
     m, n = shape
     for dtype in (torch.float32, torch.float64):
         C = inputs.uniform(m, n, seed=m + 3 * n, dtype=dtype)
