@@ -115,7 +115,10 @@ int64_t wf_ckpt_elems(int64_t m, int64_t n, int32_t ckpt_k);
  *   g_D, ldgd   m x n upstream gradient of the table, or NULL for 0.
  *   g_C, ldgc   m x n output.
  * With g_D given, the selections are recomputed and the reverse sweep runs band by band from
- * the bottom up (wf_select then wf_reverse).  With g_D = NULL the adjoint is g_score on the
+ * the bottom up (wf_select then wf_reverse); g_D and g_score must then be finite (and the
+ * sums must not overflow): the pipeline forms every routed term as a 0/1 factor times the
+ * successor's value, so an infinite or NaN value would also reach, as NaN, the cells its
+ * cell did not select.  With g_D = NULL the adjoint is g_score on the
  * cells of the argmin path traced back from cell (m-1, n-1) and exactly zero elsewhere (each
  * value being 0 + g_score, the same in any summation order), and it is computed that way:
  * the selection recompute also labels every cell with the exit of its path from its 64-row
