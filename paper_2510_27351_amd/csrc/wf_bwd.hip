@@ -211,17 +211,6 @@ __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __rest
   uint32_t pw = 0, pn = 0;
   // CAP: lane r captures its label at slot cbase + r, i.e. at step 4g + q == cl of the sub-chunk
   const int cl = CAP ? lane - (kSub * k - ls.cbase) : 0;
-  // LAB with a gradient to zero: after the sweep, 16-byte zeros over columns [64k, 64k + 64)
-  // when they all lie in the matrix (rows past the band's last fall outside the buffer
-  // range and are dropped), else element by element
-  const bool zfast = LAB && !ENTRY && po.gC != nullptr && (int64_t)kSub * k + kSub <= n;
-  __amdgpu_buffer_rsrc_t zrs = make_rsrc(nullptr, 0u);
-  int zoff = 0;
-  if (zfast) {
-    zrs = make_rsrc(static_cast<T*>(po.gC) + (int64_t)band * kBand * po.ldgc,
-                    (uint32_t)(((rows - 1) * po.ldgc + n) * (int64_t)sizeof(T)));
-    zoff = (int)(((int64_t)(lane >> 4) * po.ldgc + (int64_t)kSub * k + 4 * (lane & 15)) * (int64_t)sizeof(T));
-  }
 #pragma unroll
   for (int g = 0; g < 16; ++g) {
     if (g + 2 < 16)
@@ -293,30 +282,6 @@ __device__ __forceinline__ void sel_sub(const T* __restrict__ S, const T* __rest
       // lane r holds lane 63's label of slot 64k + r: the last row's cell of column 64k + r - 63
       const int64_t col = (int64_t)kSub * k + lane - 63;
       if (col >= 0 && col < n) po.exits[(int64_t)band * n + col] = ls.acc;
-      // zeros over the gradient's columns [64k, 64k + 64) of the band's rows (the second
-      // piece's first sub-chunk is the first piece's last); rows past the band's last fall
-      // outside the buffer range and are dropped
-      if (po.gC == nullptr) return;
-      if (zfast) {
-        // streaming (non-temporal) stores: the zeros are not read back by this sweep
-        const v4i z = {0, 0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int off = zoff + (int)((int64_t)(4 * q) * po.ldgc * (int64_t)sizeof(T));
-          __builtin_amdgcn_raw_buffer_store_b128(z, zrs, off, 0, kZeroAux);
-          if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b128(z, zrs, off + 16, 0, kZeroAux);
-        }
-        return;
-      }
-      const int64_t c0 = (int64_t)kSub * k + 4 * (lane & 15);
-      T* gb = static_cast<T*>(po.gC) + (int64_t)band * kBand * po.ldgc;
-      for (int q = 0; q < 16; ++q) {
-        const int i = 4 * q + (lane >> 4);
-        if (i >= rows) continue;
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (c0 + e < n) gb[(int64_t)i * po.ldgc + c0 + e] = T(0);
-      }
     }
   }
 }
@@ -458,9 +423,39 @@ __device__ __forceinline__ void sel_store_sub(T* S, T* Tr, const Vec4<T> (&x)[16
   Tr[(kSub * k + lane) & C::MASK] = (has_top && j < n) ? tv : E::inf();
 }
 
+// Zeros over the gradient's columns [64k, 64k + 64) of the band's rows (path adjoint with a
+// gradient to zero): 16-byte streaming stores when the columns all lie in the matrix (rows
+// past the band's last fall outside the buffer range and are dropped), else element by
+// element.
+template <typename T>
+__device__ __forceinline__ void sel_zero_sub(const PathLabels& po, int band, int rows, int64_t n, int k) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)kSub * k + 4 * (lane & 15);
+  T* gb = static_cast<T*>(po.gC) + (int64_t)band * kBand * po.ldgc;
+  if ((int64_t)kSub * k + kSub <= n) {
+    const __amdgpu_buffer_rsrc_t zrs = make_rsrc(gb, (uint32_t)(((rows - 1) * po.ldgc + n) * (int64_t)sizeof(T)));
+    const v4i z = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int off = (int)(((int64_t)(4 * q + (lane >> 4)) * po.ldgc + c0) * (int64_t)sizeof(T));
+      __builtin_amdgcn_raw_buffer_store_b128(z, zrs, off, 0, kZeroAux);
+      if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b128(z, zrs, off + 16, 0, kZeroAux);
+    }
+  } else {
+    for (int q = 0; q < 16; ++q) {
+      const int i = 4 * q + (lane >> 4);
+      if (i >= rows) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (c0 + e < n) gb[(int64_t)i * po.ldgc + c0 + e] = T(0);
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const SelArgs& a, int band, int Ks,
-                                           SelPiece pc) {
+                                           SelPiece pc, const PathLabels& po) {
   using C = SCfg<T>;
   constexpr int PF = SelPF<T>::PF;
   const int64_t ldc = opaque(a.ldc), n = opaque(a.n), m = opaque(a.m);
@@ -491,6 +486,8 @@ __device__ __forceinline__ void sel_loader(T* S, T* Tr, SelShared& sh, const Sel
     }
     sel_store_sub<T>(S, Tr, buf[p], tv[p], has_top, k, rows, n);
     lds_publish(&sh.loaded, (uint32_t)(k - k0 + 1));
+    // a piece's first sub-chunk is the previous piece's last: zeroed there
+    if (po.gC != nullptr && !(pc.second && k == k0)) sel_zero_sub<T>(po, band, rows, n, k);
     return true;
   };
   // Whole groups of PF sub-chunks carry no condition around the stores, which keeps the
@@ -527,7 +524,7 @@ __device__ __forceinline__ void sel_item(SelLds<T>& L, SelShared& sh, const SelA
   if (threadIdx.x < 64)
     sel_compute<T, LAB>(S, Tr, sh, a, band, Ks, pc, po);
   else
-    sel_loader<T>(S, Tr, sh, a, band, Ks, pc);
+    sel_loader<T>(S, Tr, sh, a, band, Ks, pc, po);
 }
 
 template <typename T>

@@ -26,8 +26,8 @@ namespace wf {
 //   caps   nb * kMaxPieces * 64 words: caps[(b * kMaxPieces + q) * 64 + r] = the label of
 //          cell (r, c) of band b, with c = (q + 1) * split - 1 for a piece q that another
 //          follows and c = n - 1 for the piece of the last band that holds column n - 1.
-//   gC, ldgc  the gradient to zero in the same sweep (its compute wave stores zeros over
-//          columns [64k, 64k + 64) of the band's rows after every sub-chunk k it sweeps), or
+//   gC, ldgc  the gradient to zero in the same sweep (its loader wave stores zeros over
+//          columns [64k, 64k + 64) of the band's rows with every sub-chunk k it stages), or
 //          null when a pass of its own zeroes it.
 constexpr int kMaxPieces = 4;  // column pieces a band's selection recompute is split into
 
