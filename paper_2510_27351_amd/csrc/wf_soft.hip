@@ -199,7 +199,15 @@ __device__ __forceinline__ T soft_cell(T yc, T ynw, T yn, T yw) {
   using M = SoftMath<T>;
   using E = Elem<T>;
   const T ymn = E::min3(ynw, yn, yw);
-  const T s = M::exp2_(ymn - ynw) + M::exp2_(ymn - yn) + M::exp2_(ymn - yw);
+  T s;
+  if constexpr (sizeof(T) == 4) {
+    // ordered as min <= median <= max, the minimum's term is exactly 1: two exponentials
+    const T ymd = __builtin_amdgcn_fmed3f(ynw, yn, yw);
+    const T ymx = __builtin_fmaxf(__builtin_fmaxf(ynw, yn), yw);
+    s = (T)1 + M::exp2_(ymn - ymd) + M::exp2_(ymn - ymx);
+  } else {
+    s = M::exp2_(ymn - ynw) + M::exp2_(ymn - yn) + M::exp2_(ymn - yw);
+  }
   const T y = yc + (ymn - M::log2_(s));
   return ymn < E::inf() ? y : E::inf();
 }
