@@ -122,11 +122,51 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t band_rsrc(const void* base, in
 }
 
 struct alignas(8) SoftShared {
-  uint32_t avail;  // handoff columns in the ring, in the consumer's order
-  uint32_t used;   // columns the compute wave has finished with
+  uint32_t avail;     // handoff columns in the ring, in the consumer's order
+  uint32_t used;      // columns the compute wave has finished with
   uint32_t item;
   uint32_t abort;
+  uint32_t produced;  // steps whose edge-row values the compute wave has put in the out ring
+  uint32_t pubd;      // steps whose values the publisher has stored
 };
+
+// Out ring: the compute wave's edge-row values (NV per step) for the publisher wave, which
+// turns them into coalesced tagged words; kPub steps.
+constexpr int kPub = 256;
+
+// The publisher wave: stores the values of steps [0, total) of the out ring as tagged words,
+// 64 steps per pass, as the compute wave produces them.  Step s holds the values of column
+// col(s) (or none, outside [0, n)); 'dst(c, v)' is the first word of value v of column c.
+template <typename T, int NV, typename Col, typename Dst>
+__device__ __forceinline__ bool publish_ring(const T* pub, SoftShared& sh, Control* ctl, int64_t n, uint32_t total,
+                                             uint32_t epoch, Col col, Dst dst) {
+  using E = Elem<T>;
+  constexpr int W = E::W;
+  const int lane = threadIdx.x & 63;
+  uint64_t waited = 0;
+  uint32_t ps = 0;
+  while (ps < total) {
+    uint32_t have;
+    if (!lds_wait_value<true, false>(&sh.produced, ps + 1, &sh.abort, ctl, waited, have)) return false;
+    const uint32_t pe = have < ps + 64 ? have : ps + 64;
+    const uint32_t st = ps + (uint32_t)lane;
+    if (st < pe) {
+      const int64_t c = col((int64_t)st);
+      if (c >= 0 && c < n) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const T x = pub[v * kPub + (int)(st & (kPub - 1))];
+          uint64_t* d = dst(c, v);
+#pragma unroll
+          for (int w = 0; w < W; ++w) store_word(d + w, tagged(E::word(x, w), epoch));
+        }
+      }
+    }
+    ps = pe;
+    lds_signal(&sh.pubd, ps);
+  }
+  return true;
+}
 
 // ---------------------------------------------------------------------------------------
 // The poller: fetches the producer band's tagged words, 64 columns per pass from the first
@@ -230,8 +270,7 @@ __device__ __forceinline__ Vec4<T> ring4(const T* ring, int64_t k0, int64_t n, T
 }
 
 template <typename T>
-__device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const SoftArgs& a, int band,
-                                                 uint32_t epoch) {
+__device__ __forceinline__ bool soft_fwd_compute(T* ring, T* pub, SoftShared& sh, const SoftArgs& a, int band) {
   using E = Elem<T>;
   constexpr int W = E::W;
   constexpr int PD = SoftPF<T>::PD;
@@ -246,7 +285,8 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const 
   // the chain runs in the scaled domain y = D * kx; stored and published values are D
   const T kx = (T)a.kx, gl = (T)a.gl;
   const bool first = band == 0;
-  const bool publish = lane == 63 && band < a.nb - 1;
+  const bool pubband = band < a.nb - 1;  // a band below reads this band's last row
+  const bool publish = lane == 63 && pubband;
   // this lane's column at step t is t - lane; group g covers steps 4g .. 4g+3.  Groups
   // [g_lo, g_hi) have every lane's four columns inside the matrix (a full band only).
   const int64_t groups = (n + 63 + 3) / 4;
@@ -281,6 +321,10 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const 
     for (int q = 0; q < 4; ++q) top.v[q] = E::inf();
   }
   for (int64_t g0 = 0; g0 < groups; g0 += PD) {
+    // the batch's out-ring slots must have been published
+    if (pubband && 4 * (g0 + PD) > kPub &&
+        !lds_wait_ge(&sh.pubd, (uint32_t)(4 * (g0 + PD) - kPub), &sh.abort, a.ctl, waited))
+      return false;
 #pragma unroll
     for (int k = 0; k < PD; ++k) {
       const int64_t g = g0 + k;
@@ -313,31 +357,26 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const 
 #pragma unroll
             for (int q = 0; q < 4; ++q) store1<T>(rd, off_d(col0 + q), out.v[q]);
           }
-          if (publish) {
-            uint64_t* dst = a.bnd + ((int64_t)band * n + col0) * W;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-              for (int w = 0; w < W; ++w) store_word(dst + q * W + w, tagged(E::word(ys.v[q], w), epoch));
-          }
         } else {
           if (live) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               if (col0 + q >= 0 && col0 + q < n) store1<T>(rd, off_d(col0 + q), out.v[q]);
-            if (i == m - 1 && col0 <= n - 1 && n - 1 <= col0 + 3) static_cast<T*>(a.score)[0] = out.v[n - 1 - col0];
-          }
-          if (publish) {
+            if (i == m - 1 && col0 <= n - 1 && n - 1 <= col0 + 3) {
+              // the score's cell by a select, not an index (an indexed element would put the
+              // whole vector in memory on every path)
+              T sc = out.v[0];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int64_t col = col0 + q;
-              if (col >= 0 && col < n) {
-#pragma unroll
-                for (int w = 0; w < W; ++w)
-                  store_word(a.bnd + ((int64_t)band * n + col) * W + w, tagged(E::word(ys.v[q], w), epoch));
-              }
+              for (int q = 1; q < 4; ++q)
+                if (n - 1 - col0 == q) sc = out.v[q];
+              static_cast<T*>(a.score)[0] = sc;
             }
           }
+        }
+        if (publish) {
+          // lane 63's values of steps 4g .. 4g+3 (columns 4g-63 ..) to the out ring
+          *reinterpret_cast<Vec4<T>*>(pub + (int)((4 * g) & (kPub - 1))) = ys;
+          lds_signal(&sh.produced, (uint32_t)(4 * g + 4));
         }
         if (!tn_ready && g + 1 < groups) {
           if (!avail_for(g + 1)) return false;
@@ -352,9 +391,10 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, SoftShared& sh, const 
 }
 
 template <typename T>
-__global__ __launch_bounds__(128) void soft_fwd_kernel(SoftArgs a) {
+__global__ __launch_bounds__(192) void soft_fwd_kernel(SoftArgs a) {
   using E = Elem<T>;
   __shared__ T ring[kRing];
+  __shared__ alignas(16) T pub[kPub];
   __shared__ SoftShared sh;
   Control* ctl = a.ctl;
   const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -363,18 +403,26 @@ __global__ __launch_bounds__(128) void soft_fwd_kernel(SoftArgs a) {
     if (threadIdx.x == 0) {
       sh.avail = 0u;
       sh.used = 0u;
+      sh.produced = 0u;
+      sh.pubd = 0u;
     }
     claim_next(ctl, &sh.item, &sh.abort);
     const int band = (int)sh.item;
     if (band >= a.nb || sh.abort != 0u) break;
     bool ok = true;
+    const int64_t n = a.n;
     if (threadIdx.x < 64) {
-      ok = soft_fwd_compute<T>(ring, sh, a, band, epoch);
-    } else if (band > 0) {
-      const int64_t n = a.n;
-      ok = poll_ring<T, 1>(ring, sh, ctl, n, epoch, [&](int64_t k) {
-        return a.bnd + ((int64_t)(band - 1) * n + k) * E::W;
-      });
+      ok = soft_fwd_compute<T>(ring, pub, sh, a, band);
+    } else if (threadIdx.x < 128) {
+      if (band > 0)
+        ok = poll_ring<T, 1>(ring, sh, ctl, n, epoch, [&](int64_t k) {
+          return a.bnd + ((int64_t)(band - 1) * n + k) * E::W;
+        });
+    } else if (band < a.nb - 1) {
+      // the last row (lane 63 handles column s - 63 at step s) for the band below
+      const uint32_t total = (uint32_t)(4 * ((n + 63 + 3) / 4));
+      ok = publish_ring<T, 1>(pub, sh, ctl, n, total, epoch, [](int64_t st) { return st - 63; },
+                              [&](int64_t c, int) { return a.bnd + ((int64_t)band * n + c) * E::W; });
     }
     if (!ok) sh.abort = 1u;
     __syncthreads();
@@ -386,8 +434,7 @@ __global__ __launch_bounds__(128) void soft_fwd_kernel(SoftArgs a) {
 // Adjoint.
 
 template <typename T>
-__device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const SoftArgs& a, int band,
-                                                 uint32_t epoch) {
+__device__ __forceinline__ bool soft_bwd_compute(T* ring, T* pub, SoftShared& sh, const SoftArgs& a, int band) {
   using E = Elem<T>;
   using M = SoftMath<T>;
   constexpr int W = E::W;
@@ -405,7 +452,8 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const 
   const bool has_gd = a.gD != nullptr;
   const T kx = (T)a.kx;
   const bool bottom = band == a.nb - 1;  // no band below: successors below are outside
-  const bool publish = lane == 0 && band > 0;
+  const bool pubband = band > 0;  // a band above reads this band's first row
+  const bool publish = lane == 0 && pubband;
   const T gs = a.gscore ? *static_cast<const T*>(a.gscore) : E::zero();
   const T NEG = -E::inf();
   // this lane's column at step t is n - 1 - t + 63 - lane; group g covers steps 4g .. 4g+3,
@@ -456,6 +504,10 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const 
     read_bottom(0, ba, bv);
   }
   for (int64_t g0 = 0; g0 < groups; g0 += PD) {
+    // the batch's out-ring slots must have been published
+    if (pubband && 4 * (g0 + PD) > kPub &&
+        !lds_wait_ge(&sh.pubd, (uint32_t)(4 * (g0 + PD) - kPub), &sh.abort, a.ctl, waited))
+      return false;
 #pragma unroll
     for (int k = 0; k < PD; ++k) {
       const int64_t g = g0 + k;
@@ -537,19 +589,13 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const 
           }
         }
         if (publish) {
+          // lane 0's (A, V) of steps 4g .. 4g+3 (columns j0 .. j0-3) to the out ring
+          Vec4<T> vs;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int64_t j = j0 - q;
-            if (j >= 0 && j < n) {
-              uint64_t* dst = a.bnd + ((int64_t)(band - 1) * n + j) * 2 * W;
-              const T vq = dg.v[3 - q] - cg.v[3 - q];
-#pragma unroll
-              for (int w = 0; w < W; ++w) {
-                store_word(dst + w, tagged(E::word(out.v[q], w), epoch));
-                store_word(dst + W + w, tagged(E::word(vq, w), epoch));
-              }
-            }
-          }
+          for (int q = 0; q < 4; ++q) vs.v[q] = dg.v[3 - q] - cg.v[3 - q];
+          *reinterpret_cast<Vec4<T>*>(pub + (int)((4 * g) & (kPub - 1))) = out;
+          *reinterpret_cast<Vec4<T>*>(pub + kPub + (int)((4 * g) & (kPub - 1))) = vs;
+          lds_signal(&sh.produced, (uint32_t)(4 * g + 4));
         }
         if (!n_ready && g + 1 < groups) {
           if (!avail_for(g + 1)) return false;
@@ -565,9 +611,10 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, SoftShared& sh, const 
 }
 
 template <typename T>
-__global__ __launch_bounds__(128) void soft_bwd_kernel(SoftArgs a) {
+__global__ __launch_bounds__(192) void soft_bwd_kernel(SoftArgs a) {
   using E = Elem<T>;
   __shared__ T ring[2 * kRing];
+  __shared__ alignas(16) T pub[2 * kPub];
   __shared__ SoftShared sh;
   Control* ctl = a.ctl;
   const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -576,20 +623,28 @@ __global__ __launch_bounds__(128) void soft_bwd_kernel(SoftArgs a) {
     if (threadIdx.x == 0) {
       sh.avail = 0u;
       sh.used = 0u;
+      sh.produced = 0u;
+      sh.pubd = 0u;
     }
     claim_next(ctl, &sh.item, &sh.abort);
     // bands from the bottom up
     const int band = a.nb - 1 - (int)sh.item;
     if ((int)sh.item >= a.nb || sh.abort != 0u) break;
     bool ok = true;
+    const int64_t n = a.n;
     if (threadIdx.x < 64) {
-      ok = soft_bwd_compute<T>(ring, sh, a, band, epoch);
-    } else if (band < a.nb - 1) {
-      const int64_t n = a.n;
+      ok = soft_bwd_compute<T>(ring, pub, sh, a, band);
+    } else if (threadIdx.x < 128) {
       // consumer column k is matrix column n-1-k of the band below's first row
-      ok = poll_ring<T, 2>(ring, sh, ctl, n, epoch, [&](int64_t k) {
-        return a.bnd + ((int64_t)band * n + (n - 1 - k)) * 2 * E::W;
-      });
+      if (band < a.nb - 1)
+        ok = poll_ring<T, 2>(ring, sh, ctl, n, epoch, [&](int64_t k) {
+          return a.bnd + ((int64_t)band * n + (n - 1 - k)) * 2 * E::W;
+        });
+    } else if (band > 0) {
+      // the first row (lane 0 handles column n + 62 - s at step s) for the band above
+      const uint32_t total = (uint32_t)(4 * ((n + 63 + 3) / 4));
+      ok = publish_ring<T, 2>(pub, sh, ctl, n, total, epoch, [n](int64_t st) { return n + 62 - st; },
+                              [&](int64_t c, int v) { return a.bnd + ((int64_t)(band - 1) * n + c) * 2 * E::W + v * E::W; });
     }
     if (!ok) sh.abort = 1u;
     __syncthreads();
@@ -601,9 +656,9 @@ __global__ __launch_bounds__(128) void soft_bwd_kernel(SoftArgs a) {
 
 hipError_t launch_soft_forward(int dtype, const SoftArgs& a, int grid, hipStream_t s) {
   if (dtype == 0)
-    hipLaunchKernelGGL(soft_fwd_kernel<float>, dim3(grid), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(soft_fwd_kernel<float>, dim3(grid), dim3(192), 0, s, a);
   else if (dtype == 1)
-    hipLaunchKernelGGL(soft_fwd_kernel<double>, dim3(grid), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(soft_fwd_kernel<double>, dim3(grid), dim3(192), 0, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -611,9 +666,9 @@ hipError_t launch_soft_forward(int dtype, const SoftArgs& a, int grid, hipStream
 
 hipError_t launch_soft_backward(int dtype, const SoftArgs& a, int grid, hipStream_t s) {
   if (dtype == 0)
-    hipLaunchKernelGGL(soft_bwd_kernel<float>, dim3(grid), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(soft_bwd_kernel<float>, dim3(grid), dim3(192), 0, s, a);
   else if (dtype == 1)
-    hipLaunchKernelGGL(soft_bwd_kernel<double>, dim3(grid), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(soft_bwd_kernel<double>, dim3(grid), dim3(192), 0, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
