@@ -263,6 +263,8 @@ struct SoftPF {
 // plane), or 'fill' past the last column.
 template <typename T>
 __device__ __forceinline__ Vec4<T> ring4(const T* ring, int64_t k0, int64_t n, T fill) {
+  // k0 is a multiple of 4: four whole columns are one aligned vector of the ring
+  if (k0 + 4 <= n) return *reinterpret_cast<const Vec4<T>*>(ring + (int)(k0 & (kRing - 1)));
   Vec4<T> v;
 #pragma unroll
   for (int q = 0; q < 4; ++q) v.v[q] = k0 + q < n ? ring[(int)((k0 + q) & (kRing - 1))] : fill;
@@ -393,7 +395,7 @@ __device__ __forceinline__ bool soft_fwd_compute(T* ring, T* pub, SoftShared& sh
 template <typename T>
 __global__ __launch_bounds__(192) void soft_fwd_kernel(SoftArgs a) {
   using E = Elem<T>;
-  __shared__ T ring[kRing];
+  __shared__ alignas(16) T ring[kRing];
   __shared__ alignas(16) T pub[kPub];
   __shared__ SoftShared sh;
   Control* ctl = a.ctl;
@@ -613,7 +615,7 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, T* pub, SoftShared& sh
 template <typename T>
 __global__ __launch_bounds__(192) void soft_bwd_kernel(SoftArgs a) {
   using E = Elem<T>;
-  __shared__ T ring[2 * kRing];
+  __shared__ alignas(16) T ring[2 * kRing];
   __shared__ alignas(16) T pub[2 * kPub];
   __shared__ SoftShared sh;
   Control* ctl = a.ctl;
