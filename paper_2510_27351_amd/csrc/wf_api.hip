@@ -367,6 +367,7 @@ int wf_forward(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, void
   a.ctl = ws->ctl;
   a.bnd = ws->bnd;
   a.trace = (g_trace && dev == g_trace_dev && nb <= g_trace_bands) ? g_trace : nullptr;
+  a.kx = a.gl = 1.0;
   const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
   const int tile = choose_tile(dtype, m, n, false);
   hipError_t e = launch_forward(dtype, tile, a, grid, static_cast<hipStream_t>(stream));
@@ -417,6 +418,7 @@ int wf_forward_noalloc(int dtype, int64_t m, int64_t n, const void* C, int64_t l
   a.ctl = ctl;
   a.bnd = reinterpret_cast<uint64_t*>(sd.ptr + kScratchCtl);
   a.trace = nullptr;
+  a.kx = a.gl = 1.0;
   const int grid = (int)std::min<int64_t>(nb, sd.num_cus);
   hipError_t e = launch_forward(dtype, choose_tile(dtype, m, n, false), a, grid, st);
   return e == hipSuccess ? WF_OK : WF_E_DEVICE;
@@ -671,22 +673,26 @@ int wf_soft_forward(int dtype, int64_t m, int64_t n, double gamma, const void* C
   rc = ensure_ws_on(dev, static_cast<hipStream_t>(stream), (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * words_per_elem(dtype),
                     &ws);
   if (rc != WF_OK) return rc;
-  SoftArgs a;
+  // the min-plus forward's band pipeline with the soft-min cell (64-row bands)
+  FwdArgs a;
   std::memset(&a, 0, sizeof(a));
   a.C = C;
   a.D = D;
   a.score = score;
+  a.ckpt = nullptr;
   a.ldc = ldc;
   a.ldd = ldd;
   a.m = m;
   a.n = n;
+  a.ckpt_k = 0;
   a.nb = (int32_t)nb;
-  a.kx = 1.0 / (gamma * std::log(2.0));
-  a.gl = gamma * std::log(2.0);
   a.ctl = ws->ctl;
   a.bnd = ws->bnd;
-  const int grid = (int)std::min<int64_t>(nb, 4 * (int64_t)ws->num_cus);
-  return launch_soft_forward(dtype, a, grid, static_cast<hipStream_t>(stream)) == hipSuccess ? WF_OK : WF_E_DEVICE;
+  a.trace = nullptr;
+  a.kx = 1.0 / (gamma * std::log(2.0));
+  a.gl = gamma * std::log(2.0);
+  const int grid = (int)std::min<int64_t>(nb, ws->num_cus);
+  return launch_forward_soft(dtype, a, grid, static_cast<hipStream_t>(stream)) == hipSuccess ? WF_OK : WF_E_DEVICE;
 }
 
 int wf_soft_backward(int dtype, int64_t m, int64_t n, double gamma, const void* C, int64_t ldc, const void* D,

@@ -41,6 +41,7 @@
 // the critical path of the whole sweep.  G (16/32/64, the "tile width") is the handoff
 // granularity.
 #include "wf_common.h"
+#include "wf_soft.h"
 
 namespace wf {
 namespace {
@@ -141,9 +142,24 @@ __device__ __forceinline__ void load_group(const T* __restrict__ S, const T* __r
 // DPP wave_shr:1 whose "old" operand fills lane 0: for sub-band 0 the top row's value, for
 // sub-band k >= 1 lane 63 of sub-band k-1 from two steps back; NW is the previous N.  Per
 // cell one DPP move, one v_min3, one add, all lanes' chains independent within the step.
-template <typename T, int G, int R>
-__device__ __forceinline__ void cells4(ComputeState<T, G, R>& st, const GroupRegs<T, G, R>& r, Vec4<T> (&out)[R]) {
+//
+// SOFT: the soft-min cell instead (one sub-band only), on values in the scaled domain
+// y = D log2(e) / gamma; kx scales the cell's input C the same way.
+template <typename T, int G, int R, bool SOFT>
+__device__ __forceinline__ void cells4(ComputeState<T, G, R>& st, const GroupRegs<T, G, R>& r, Vec4<T> (&out)[R],
+                                       T kx) {
   using E = Elem<T>;
+  if constexpr (SOFT) {
+    static_assert(R == 1, "the soft-min sweep uses one sub-band per band");
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T N = E::shr1(st.X[0], r.t.v[q]);
+      st.X[0] = soft_cell<T>(r.c[0].v[q] * kx, st.NW[0], N, st.X[0]);
+      st.NW[0] = N;
+      out[0].v[q] = st.X[0];
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     T N[R], Qn[R];
@@ -190,11 +206,11 @@ __device__ __forceinline__ bool unit_wait(int u, Shared& sh, Control* ctl, uint6
 // earlier would hold back the last steps of unit u, and with them the band's last row,
 // until the band above has delivered unit u+1: one unit of extra lag per band.  After the
 // last unit the reads wrap around the ring and are not used.
-template <typename T, int G, int R>
+template <typename T, int G, int R, bool SOFT>
 __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restrict__ Tr, Shared& sh, Control* ctl,
                                              int u, int Us, ComputeState<T, G, R>& st, const UnitRegs<T, G, R>& in,
                                              UnitRegs<T, G, R>& out, uint32_t& stall_c, uint32_t& stall_t,
-                                             uint64_t& waited, bool trace) {
+                                             uint64_t& waited, bool trace, T kx) {
   using C = FwdCfg<T, G, R>;
   constexpr int NG = C::NG;
   const int lane = threadIdx.x & 63;
@@ -227,7 +243,7 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
     // gathers the reads of several groups into one burst just before the first of them)
     __builtin_amdgcn_sched_barrier(0);
     Vec4<T> d[R];
-    cells4<T, G, R>(st, gr[g], d);
+    cells4<T, G, R, SOFT>(st, gr[g], d, kx);
 #pragma unroll
     for (int k = 0; k < R; ++k) *reinterpret_cast<Vec4<T>*>(S + (k * kBand + lane) * C::PITCH + base + 4 * g) = d[k];
   }
@@ -245,9 +261,9 @@ __device__ __forceinline__ bool compute_unit(T* __restrict__ S, const T* __restr
   return true;
 }
 
-template <typename T, int G, int R>
+template <typename T, int G, int R, bool SOFT>
 __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restrict__ Tr, Shared& sh, Control* ctl,
-                                             int Us, bool first_band, uint64_t* trace) {
+                                             int Us, bool first_band, uint64_t* trace, T kx) {
   using E = Elem<T>;
   const int lane = threadIdx.x & 63;
   ComputeState<T, G, R> st;
@@ -275,7 +291,7 @@ __device__ __forceinline__ void compute_band(T* __restrict__ S, const T* __restr
   // unit's there (they are dead by the time those reads are issued, so both use the same
   // registers and nothing is copied at the back edge).
   for (int u = 0; u < Us; ++u) {
-    if (!compute_unit<T, G, R>(S, Tr, sh, ctl, u, Us, st, P, P, stall_c, stall_t, waited, tr)) {
+    if (!compute_unit<T, G, R, SOFT>(S, Tr, sh, ctl, u, Us, st, P, P, stall_c, stall_t, waited, tr, kx)) {
       sh.abort = 1u;
       return;
     }
@@ -509,10 +525,20 @@ __device__ __forceinline__ void top_band(const T* S, T* Tr, Shared& sh, const Fw
 }
 
 // ---------------------------------------------------------------------------------------
-// wave 3: storer
-template <typename T, int G, int R>
+// wave 3: storer.  SOFT: the ring holds scaled values; D = y * gl (gl = gamma ln 2).
+template <typename T, int R, bool SOFT>
+__device__ __forceinline__ void unscale(Vec4<T> (&v)[16], T gl) {
+  if constexpr (SOFT) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[k].v[e] *= gl;
+  }
+}
+
+template <typename T, int G, int R, bool SOFT>
 __device__ __forceinline__ void store_sub(const T* S, __amdgpu_buffer_rsrc_t drs, int64_t ldd, int64_t n, int rows,
-                                          int s) {
+                                          int s, T gl) {
   using C = FwdCfg<T, G, R>;
   typedef int v4i __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
@@ -528,6 +554,7 @@ __device__ __forceinline__ void store_sub(const T* S, __amdgpu_buffer_rsrc_t drs
         const int i = 64 * h + 4 * k + (lane >> 4);
         v[k] = *reinterpret_cast<const Vec4<T>*>(S + i * C::PITCH + slot);
       }
+      unscale<T, R, SOFT>(v, gl);
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int i = 64 * h + 4 * k + (lane >> 4);
@@ -555,6 +582,7 @@ __device__ __forceinline__ void store_sub(const T* S, __amdgpu_buffer_rsrc_t drs
       const int i = 64 * h + 4 * k + (lane >> 4);
       v[k] = *reinterpret_cast<const Vec4<T>*>(S + i * C::PITCH + slot);
     }
+    unscale<T, R, SOFT>(v, gl);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int i = 64 * h + 4 * k + (lane >> 4);
@@ -587,7 +615,7 @@ __device__ __forceinline__ void store_sub(const T* S, __amdgpu_buffer_rsrc_t drs
   }
 }
 
-template <typename T, int G, int R>
+template <typename T, int G, int R, bool SOFT>
 __device__ __forceinline__ void store_band(const T* S, Shared& sh, const FwdArgs& a, int band, int Ks,
                                            uint64_t* tr) {
   using C = FwdCfg<T, G, R>;
@@ -598,6 +626,7 @@ __device__ __forceinline__ void store_band(const T* S, Shared& sh, const FwdArgs
   T* ck_cols = a.ckpt ? static_cast<T*>(a.ckpt) + ((m + kBand - 1) / kBand - 1) * n : nullptr;
   const int K = a.ckpt_k;
   const int64_t sc_row = m - 1 - row0;  // band row of the score, if it lies in this band
+  const T gl = SOFT ? (T)a.gl : T(1);
   const __amdgpu_buffer_rsrc_t drs =
       make_rsrc(a.D ? static_cast<T*>(a.D) + row0 * ldd : nullptr,
                 a.D ? (uint32_t)(((rows - 1) * ldd + n) * (int64_t)sizeof(T)) : 0u);
@@ -610,7 +639,7 @@ __device__ __forceinline__ void store_band(const T* S, Shared& sh, const FwdArgs
       sh.abort = 1u;
       return;
     }
-    if (a.D) store_sub<T, G, R>(S, drs, ldd, n, rows, s);
+    if (a.D) store_sub<T, G, R, SOFT>(S, drs, ldd, n, rows, s, gl);
     if (ck_cols) {
 #pragma unroll
       for (int h = 0; h < R; ++h) {
@@ -626,7 +655,10 @@ __device__ __forceinline__ void store_band(const T* S, Shared& sh, const FwdArgs
     }
     if (sc_row >= 0 && sc_row < C::H && lane == (int)(sc_row % kBand)) {
       const int64_t slot = n - 1 + C::skew((int)sc_row);
-      if (slot / kSub == s) *static_cast<T*>(a.score) = S[sc_row * C::PITCH + ((int)slot & C::MASK)];
+      if (slot / kSub == s) {
+        const T y = S[sc_row * C::PITCH + ((int)slot & C::MASK)];
+        *static_cast<T*>(a.score) = SOFT ? y * gl : y;
+      }
     }
     lds_publish(&sh.ctr[3], (uint32_t)(s + 1));
   }
@@ -692,7 +724,7 @@ __device__ __forceinline__ void publish_band(const T* S, Shared& sh, const FwdAr
 
 // ---------------------------------------------------------------------------------------
 // One band of one instance, all five roles.  The LDS counters must be zero on entry.
-template <typename T, int G, int R>
+template <typename T, int G, int R, bool SOFT = false>
 __device__ __forceinline__ void run_band(T* S, T* Tr, Shared& sh, const FwdArgs& a, int band, uint32_t epoch,
                                          uint64_t* tr) {
   using C = FwdCfg<T, G, R>;
@@ -702,7 +734,7 @@ __device__ __forceinline__ void run_band(T* S, T* Tr, Shared& sh, const FwdArgs&
   const int Us = Ks * C::GPS;                                          // compute / publish units
   const int Ut = (int)((a.n + G - 1) / G);                             // top units holding real columns
   if (wave == 0) {
-    compute_band<T, G, R>(S, Tr, sh, a.ctl, Us, band == 0, tr);
+    compute_band<T, G, R, SOFT>(S, Tr, sh, a.ctl, Us, band == 0, tr, SOFT ? (T)a.kx : T(1));
   } else if (wave == 1) {
     loader_band<T, G, R>(S, sh, a, band, Ks, tr);
   } else if (wave == 2) {
@@ -711,7 +743,7 @@ __device__ __forceinline__ void run_band(T* S, T* Tr, Shared& sh, const FwdArgs&
     // them loaded so that the compute wave's readiness test stays one comparison.
     if ((threadIdx.x & 63) == 0 && sh.abort == 0u) lds_signal(&sh.ctr[1], 0x7fffffffu);
   } else if (wave == 3) {
-    store_band<T, G, R>(S, sh, a, band, Ks, tr);
+    store_band<T, G, R, SOFT>(S, sh, a, band, Ks, tr);
   } else {
     publish_band<T, G, R>(S, sh, a, band, Us, epoch, tr);
   }
@@ -719,7 +751,7 @@ __device__ __forceinline__ void run_band(T* S, T* Tr, Shared& sh, const FwdArgs&
 
 // TRACE = false compiles every trace statement out (the production instance); the traced
 // instance is launched only while tracing is enabled.
-template <typename T, int G, int R, bool TRACE>
+template <typename T, int G, int R, bool TRACE, bool SOFT = false>
 __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
   using C = FwdCfg<T, G, R>;
   if constexpr (!TRACE) a.trace = nullptr;
@@ -744,7 +776,7 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
       tr[6] = xcc;
       tr[7] = blockIdx.x;
     }
-    run_band<T, G, R>(S, Tr, sh, a, band, epoch, tr);
+    run_band<T, G, R, SOFT>(S, Tr, sh, a, band, epoch, tr);
     if (tr && threadIdx.x == 3 * 64) tr[3] = __builtin_amdgcn_s_memrealtime();
     __syncthreads();
   }
@@ -787,6 +819,7 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_batch_kernel(BatchArgs b) {
     a.ctl = ctl;
     a.bnd = b.bnd + in.bnd_off;
     a.trace = nullptr;
+    a.kx = a.gl = 1.0;
     run_band<T, G, R>(S, Tr, sh, a, it.band, epoch, nullptr);
     __syncthreads();
   }
@@ -837,6 +870,17 @@ hipError_t launch_forward(int dtype, int tile, const FwdArgs& a, int grid, hipSt
     case 2: return launch_t<int32_t, kRowsF>(tile, a, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// The soft-min sweep's steps cost several times a min-plus step (exponentials and a
+// logarithm per cell), so the finest handoff unit, 16 columns, serves it best.
+hipError_t launch_forward_soft(int dtype, const FwdArgs& a, int grid, hipStream_t s) {
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL((fwd_kernel<float, 16, 1, false, true>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((fwd_kernel<double, 16, 1, false, true>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_forward_batch(int dtype, int tile, int rows, const BatchArgs& b, int grid, hipStream_t s) {

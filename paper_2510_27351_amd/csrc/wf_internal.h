@@ -45,6 +45,9 @@ struct FwdArgs {
   Control* ctl;
   uint64_t* bnd;    // (nb-1) * n * words-per-element handoff words (last row of each band)
   uint64_t* trace;  // null, or kTraceWords words per band (see wf_trace_enable)
+  // soft-min sweep only: kx = log2(e) / gamma scales C into the base-2 domain the cells run
+  // in, gl = gamma ln 2 scales the results back to D
+  double kx, gl;
 };
 
 // Per-band trace record, written when tracing is enabled (times in ticks of the 100 MHz

@@ -10,14 +10,15 @@
 // with V(succ) = D(succ) - C(succ) the successor's soft minimum, so the weight is the
 // derivative of the successor's soft minimum with respect to D[i][j].  gC = A.
 //
-// Both sweeps are persistent band pipelines like the min-plus ones, in a lighter form: a
-// workgroup of two waves per 64-row band, claimed in order (top-down forward, bottom-up for
-// the adjoint).  The compute wave runs the skewed wavefront (lane r owns band row r; at step
-// t it handles column t - r forward, n - 1 - t + 63 - r backward), taking the lane-shifted
-// neighbour values through DPP and reading its inputs straight from global memory as
-// 16-byte range-checked buffer loads of four consecutive columns, issued two 4-step groups
-// ahead.  The band's edge row goes to the next band as epoch-tagged 64-bit words (the
-// forward's last row; the adjoint's first row as (A, V) pairs); the second wave polls them
+// The forward runs in the min-plus forward's band pipeline (wf_fwd.hip) with the soft-min
+// cell in place of the minimum; this file holds the adjoint.  It is a persistent band
+// pipeline in a lighter form: a workgroup of three waves per 64-row band, claimed bottom-up.
+// The compute wave runs the skewed wavefront (lane r owns band row r; at step t it handles
+// column n - 1 - t + 63 - r), taking the lane-shifted neighbour values through DPP and
+// reading its inputs straight from global memory as 16-byte range-checked buffer loads of
+// four consecutive columns, issued two 4-step groups ahead.  The band's first row goes to
+// the band above as epoch-tagged 64-bit (A, V) word pairs: the compute wave writes it to an
+// LDS out ring and a publisher wave stores it; a poller wave reads the band below's words
 // into an LDS ring that the compute wave reads.  Every wait is bounded.
 #include "wf_common.h"
 #include "wf_soft.h"
@@ -26,22 +27,6 @@ namespace wf {
 namespace {
 
 constexpr int kRing = 1024;  // handoff ring: columns
-
-template <typename T>
-struct SoftMath;
-// float: the hardware base-2 exponential and logarithm (v_exp_f32, v_log_f32, about one
-// ulp).  The logarithm's argument is a sum in [1, 3]; an exponential that would be
-// subnormal (a weight below 2^-126) reads as 0, which changes no sum it enters.
-template <>
-struct SoftMath<float> {
-  __device__ static __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
-  __device__ static __forceinline__ float log2_(float x) { return __builtin_amdgcn_logf(x); }
-};
-template <>
-struct SoftMath<double> {
-  __device__ static __forceinline__ double exp2_(double x) { return exp2(x); }
-  __device__ static __forceinline__ double log2_(double x) { return log2(x); }
-};
 
 // Four consecutive columns of one row, as one (float) or two (double) 16-byte transfers.
 template <typename T>
@@ -230,28 +215,6 @@ __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl,
 // ---------------------------------------------------------------------------------------
 // Forward.
 
-// One cell in the scaled domain y = D log2(e) / gamma: the soft minimum of the scaled
-// neighbours is ymn - log2(sum_k 2^(ymn - y_k)) with ymn their minimum, and the cell's value
-// adds the scaled input yc.  Three inputs of +inf (the padding lanes before column 0) give
-// +inf, not NaN.
-template <typename T>
-__device__ __forceinline__ T soft_cell(T yc, T ynw, T yn, T yw) {
-  using M = SoftMath<T>;
-  using E = Elem<T>;
-  const T ymn = E::min3(ynw, yn, yw);
-  T s;
-  if constexpr (sizeof(T) == 4) {
-    // ordered as min <= median <= max, the minimum's term is exactly 1: two exponentials
-    const T ymd = __builtin_amdgcn_fmed3f(ynw, yn, yw);
-    const T ymx = __builtin_fmaxf(__builtin_fmaxf(ynw, yn), yw);
-    s = (T)1 + M::exp2_(ymn - ymd) + M::exp2_(ymn - ymx);
-  } else {
-    s = M::exp2_(ymn - ynw) + M::exp2_(ymn - yn) + M::exp2_(ymn - yw);
-  }
-  const T y = yc + (ymn - M::log2_(s));
-  return ymn < E::inf() ? y : E::inf();
-}
-
 // 4-step groups of inputs in flight: the chain takes tens of nanoseconds per step, so the
 // loads must be issued a memory latency (1-2 us under load) ahead of their use.
 template <typename T>
@@ -269,167 +232,6 @@ __device__ __forceinline__ Vec4<T> ring4(const T* ring, int64_t k0, int64_t n, T
 #pragma unroll
   for (int q = 0; q < 4; ++q) v.v[q] = k0 + q < n ? ring[(int)((k0 + q) & (kRing - 1))] : fill;
   return v;
-}
-
-template <typename T>
-__device__ __forceinline__ bool soft_fwd_compute(T* ring, T* pub, SoftShared& sh, const SoftArgs& a, int band) {
-  using E = Elem<T>;
-  constexpr int W = E::W;
-  constexpr int PD = SoftPF<T>::PD;
-  const int lane = threadIdx.x & 63;
-  const int64_t m = a.m, n = a.n;
-  const int64_t row0 = (int64_t)band * kBand;
-  const int rows = (int)(m - row0 < kBand ? m - row0 : kBand);
-  const int64_t i = row0 + lane;
-  const bool live = lane < rows;
-  const auto rc = band_rsrc<T>(a.C, row0, rows, a.ldc, n);
-  const auto rd = band_rsrc<T>(a.D, row0, rows, a.ldd, n);
-  // the chain runs in the scaled domain y = D * kx; stored and published values are D
-  const T kx = (T)a.kx, gl = (T)a.gl;
-  const bool first = band == 0;
-  const bool pubband = band < a.nb - 1;  // a band below reads this band's last row
-  const bool publish = lane == 63 && pubband;
-  // this lane's column at step t is t - lane; group g covers steps 4g .. 4g+3.  Groups
-  // [g_lo, g_hi) have every lane's four columns inside the matrix (a full band only).
-  const int64_t groups = (n + 63 + 3) / 4;
-  const int64_t g_lo = rows == kBand ? 16 : groups, g_hi = rows == kBand ? n / 4 : 0;
-  auto off_c = [&](int64_t g) -> uint32_t { return (uint32_t)(((int64_t)lane * a.ldc + 4 * g - lane) * sizeof(T)); };
-  auto off_d = [&](int64_t col) -> uint32_t { return (uint32_t)(((int64_t)lane * a.ldd + col) * sizeof(T)); };
-  T Y = E::inf(), NW = (first && lane == 0) ? E::zero() : E::inf();
-  Vec4<T> cb[PD];
-#pragma unroll
-  for (int k = 0; k < PD; ++k) cb[k] = load4<T>(rc, off_c(k));
-  uint64_t waited = 0;
-  // top-row columns known to be in the ring (wave-uniform); the first band's top row is
-  // virtual (+inf) and needs no ring
-  uint32_t have = first ? 0xffffffffu : 0u;
-  auto avail_for = [&](int64_t g) -> bool {  // waits until group g's top columns are in the ring
-    const int64_t need = 4 * g + 4 < n ? 4 * g + 4 : n;
-    if (need <= (int64_t)have) return true;
-    have = lds_load(&sh.avail);
-    if (need <= (int64_t)have) return true;
-    uint32_t seen;
-    if (!lds_wait_value<true, false>(&sh.avail, (uint32_t)need, &sh.abort, a.ctl, waited, seen)) return false;
-    have = seen;
-    return true;
-  };
-  // the band above's published values are scaled (y); +inf past the matrix
-  Vec4<T> top;
-  if (!first) {
-    if (!avail_for(0)) return false;
-    top = ring4<T>(ring, 0, n, E::inf());
-  } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) top.v[q] = E::inf();
-  }
-  for (int64_t g0 = 0; g0 < groups; g0 += PD) {
-    // the batch's out-ring slots must have been published
-    if (pubband && 4 * (g0 + PD) > kPub &&
-        !lds_wait_ge(&sh.pubd, (uint32_t)(4 * (g0 + PD) - kPub), &sh.abort, a.ctl, waited))
-      return false;
-#pragma unroll
-    for (int k = 0; k < PD; ++k) {
-      const int64_t g = g0 + k;
-      if (g < groups) {
-        const Vec4<T> cg = cb[k];
-        cb[k] = load4<T>(rc, off_c(g + PD));
-        Vec4<T> tnext = top;
-        bool tn_ready = first;
-        if (!first && g + 1 < groups && 4 * g + 8 <= (int64_t)have) {
-          tnext = ring4<T>(ring, 4 * g + 4, n, E::inf());
-          tn_ready = true;
-        }
-        Vec4<T> ys, out;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T N = E::shr1(Y, top.v[q]);
-          Y = soft_cell<T>(cg.v[q] * kx, NW, N, Y);
-          NW = N;
-          ys.v[q] = Y;
-          out.v[q] = Y * gl;
-        }
-        const int64_t col0 = 4 * g - lane;  // columns col0 .. col0+3 of row i
-        if (g >= g_lo && g < g_hi) {
-          // interior group: every cell of every lane lies in the matrix (the last cell, which
-          // holds the score, is never in one)
-          if constexpr (sizeof(T) == 4) {
-            __builtin_amdgcn_raw_buffer_store_b128(
-                __builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, out), rd, off_d(col0), 0, 0);
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) store1<T>(rd, off_d(col0 + q), out.v[q]);
-          }
-        } else {
-          if (live) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (col0 + q >= 0 && col0 + q < n) store1<T>(rd, off_d(col0 + q), out.v[q]);
-            if (i == m - 1 && col0 <= n - 1 && n - 1 <= col0 + 3) {
-              // the score's cell by a select, not an index (an indexed element would put the
-              // whole vector in memory on every path)
-              T sc = out.v[0];
-#pragma unroll
-              for (int q = 1; q < 4; ++q)
-                if (n - 1 - col0 == q) sc = out.v[q];
-              static_cast<T*>(a.score)[0] = sc;
-            }
-          }
-        }
-        if (publish) {
-          // lane 63's values of steps 4g .. 4g+3 (columns 4g-63 ..) to the out ring
-          *reinterpret_cast<Vec4<T>*>(pub + (int)((4 * g) & (kPub - 1))) = ys;
-          lds_signal(&sh.produced, (uint32_t)(4 * g + 4));
-        }
-        if (!tn_ready && g + 1 < groups) {
-          if (!avail_for(g + 1)) return false;
-          tnext = ring4<T>(ring, 4 * g + 4, n, E::inf());
-        }
-        top = tnext;
-      }
-    }
-    if (!first && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * (g0 + PD) < n ? 4 * (g0 + PD) : n));
-  }
-  return true;
-}
-
-template <typename T>
-__global__ __launch_bounds__(192) void soft_fwd_kernel(SoftArgs a) {
-  using E = Elem<T>;
-  __shared__ alignas(16) T ring[kRing];
-  __shared__ alignas(16) T pub[kPub];
-  __shared__ SoftShared sh;
-  Control* ctl = a.ctl;
-  const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (threadIdx.x == 0) sh.abort = 0u;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      sh.avail = 0u;
-      sh.used = 0u;
-      sh.produced = 0u;
-      sh.pubd = 0u;
-    }
-    claim_next(ctl, &sh.item, &sh.abort);
-    const int band = (int)sh.item;
-    if (band >= a.nb || sh.abort != 0u) break;
-    bool ok = true;
-    const int64_t n = a.n;
-    if (threadIdx.x < 64) {
-      ok = soft_fwd_compute<T>(ring, pub, sh, a, band);
-    } else if (threadIdx.x < 128) {
-      if (band > 0)
-        ok = poll_ring<T, 1>(ring, sh, ctl, n, epoch, [&](int64_t k) {
-          return a.bnd + ((int64_t)(band - 1) * n + k) * E::W;
-        });
-    } else if (band < a.nb - 1) {
-      // the last row (lane 63 handles column s - 63 at step s) for the band below
-      const uint32_t total = (uint32_t)(4 * ((n + 63 + 3) / 4));
-      ok = publish_ring<T, 1>(pub, sh, ctl, n, total, epoch, [](int64_t st) { return st - 63; },
-                              [&](int64_t c, int) { return a.bnd + ((int64_t)band * n + c) * E::W; });
-    }
-    if (!ok) sh.abort = 1u;
-    __syncthreads();
-  }
-  finish_launch(ctl, epoch);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -655,16 +457,6 @@ __global__ __launch_bounds__(192) void soft_bwd_kernel(SoftArgs a) {
 }
 
 }  // namespace
-
-hipError_t launch_soft_forward(int dtype, const SoftArgs& a, int grid, hipStream_t s) {
-  if (dtype == 0)
-    hipLaunchKernelGGL(soft_fwd_kernel<float>, dim3(grid), dim3(192), 0, s, a);
-  else if (dtype == 1)
-    hipLaunchKernelGGL(soft_fwd_kernel<double>, dim3(grid), dim3(192), 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
 
 hipError_t launch_soft_backward(int dtype, const SoftArgs& a, int grid, hipStream_t s) {
   if (dtype == 0)

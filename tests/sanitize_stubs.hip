@@ -9,7 +9,7 @@ namespace wf {
 hipError_t launch_forward(int, int, const FwdArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_select(int, const SelArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_adjoint(int, int, const AdjArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_soft_forward(int, const SoftArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_forward_soft(int, const FwdArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_soft_backward(int, const SoftArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_select_path(int, const SelArgs&, const PathLabels&, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_zero(int, void*, int64_t, int64_t, int64_t, int, hipStream_t) { return hipErrorInvalidValue; }
