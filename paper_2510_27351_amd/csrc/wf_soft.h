@@ -30,21 +30,23 @@ hipError_t launch_soft_backward(int dtype, const SoftArgs& a, int grid, hipStrea
 // soft-min cell: a.kx, a.gl set, no checkpoint grid.
 hipError_t launch_forward_soft(int dtype, const FwdArgs& a, int grid, hipStream_t s);
 
-// Base-2 exponential and logarithm of the soft minimum.  float: the hardware functions
-// (v_exp_f32, v_log_f32, about one ulp); the logarithm's argument is a sum in [1, 3] and an
-// exponential that would be subnormal (a weight below 2^-126) reads as 0, which changes no
-// sum it enters.
+// Base-2 exponential and logarithm of the soft minimum, and the adjoint's fused multiply-add,
+// all in the element type.  float: the hardware functions (v_exp_f32, v_log_f32, about one
+// ulp); the logarithm's argument is a sum in [1, 3] and an exponential that would be
+// subnormal (a weight below 2^-126) reads as 0, which changes no sum it enters.
 template <typename T>
 struct SoftMath;
 template <>
 struct SoftMath<float> {
   __device__ static __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
   __device__ static __forceinline__ float log2_(float x) { return __builtin_amdgcn_logf(x); }
+  __device__ static __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 };
 template <>
 struct SoftMath<double> {
   __device__ static __forceinline__ double exp2_(double x) { return exp2(x); }
   __device__ static __forceinline__ double log2_(double x) { return log2(x); }
+  __device__ static __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 };
 
 // One cell in the scaled domain y = D log2(e) / gamma: the soft minimum of the scaled

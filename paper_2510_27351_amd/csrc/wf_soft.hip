@@ -27,6 +27,7 @@ namespace wf {
 namespace {
 
 constexpr int kRing = 1024;  // handoff ring: columns
+constexpr int kFill = 128;   // fill columns after the last one (at least the groups' overhang)
 
 // Four consecutive columns of one row, as one (float) or two (double) 16-byte transfers.
 template <typename T>
@@ -46,29 +47,6 @@ __device__ __forceinline__ Vec4<T> load4(__amdgpu_buffer_rsrc_t r, uint32_t off)
     __builtin_memcpy(&v, w, sizeof(v));
   }
   return v;
-}
-
-// Four columns col .. col+3 of this lane's row (lane * ld elements into the resource).  A
-// start before the resource (only lane 0 near the left edge of the adjoint's last groups,
-// columns below 0) loads from offset 0 and moves the columns into place; the slots before
-// column 0 hold no data and are never used.
-template <typename T>
-__device__ __forceinline__ Vec4<T> load4_at(__amdgpu_buffer_rsrc_t r, int64_t ld, int lane, int64_t col) {
-  const int64_t e = (int64_t)lane * ld + col;
-  const Vec4<T> v = load4<T>(r, e >= 0 ? (uint32_t)(e * (int64_t)sizeof(T)) : 0u);
-  if (!__any(e < 0)) return v;  // wave-uniform: the shift is needed in the last groups only
-  const int sh = e < 0 ? (int)-e : 0;
-  Vec4<T> o = v;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    T x = v.v[0];
-#pragma unroll
-    for (int p = 0; p < q; ++p)
-      if (q - sh == p) x = v.v[p];
-    if (sh == 0) x = v.v[q];
-    o.v[q] = x;
-  }
-  return o;
 }
 
 // wave_shl:1 -- lane r receives lane r+1's value; lane 63 keeps 'old'.
@@ -113,6 +91,9 @@ struct alignas(8) SoftShared {
   uint32_t abort;
   uint32_t produced;  // steps whose edge-row values the compute wave has put in the out ring
   uint32_t pubd;      // steps whose values the publisher has stored
+  uint32_t ld[2];     // adjoint: sub-chunks of D and of C staged in LDS
+  uint32_t done;      // adjoint: sub-chunks the compute wave has finished
+  uint32_t stored;    // adjoint: sub-chunks of gC the storer has written back
 };
 
 // Out ring: the compute wave's edge-row values (NV per step) for the publisher wave, which
@@ -160,7 +141,7 @@ __device__ __forceinline__ bool publish_ring(const T* pub, SoftShared& sh, Contr
 // of the first word of consumer column k.
 template <typename T, int NV, typename WordAt>
 __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl, int64_t n, uint32_t epoch,
-                                          WordAt word_at) {
+                                          const T (&fill)[NV], WordAt word_at) {
   using E = Elem<T>;
   constexpr int W = E::W;
   const int lane = threadIdx.x & 63;
@@ -174,17 +155,25 @@ __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl,
     const int64_t k = u + lane;
     const bool real = k < n;
     const uint64_t* src = real ? word_at(k) : reinterpret_cast<const uint64_t*>(ctl) + 4;
-    uint64_t x[NV * W];
+    // Two polls in flight: while one pass's words are checked, the next pass's are on their
+    // way, so readiness is seen about half a round trip sooner than with one.
+    uint64_t xa[NV * W], xb[NV * W];
+    auto issue = [&](uint64_t (&x)[NV * W]) {
 #pragma unroll
-    for (int q = 0; q < NV * W; ++q) x[q] = load_word(src + q);
-    bool ok = true;
+      for (int q = 0; q < NV * W; ++q) x[q] = load_word(src + q);
+    };
+    // the leading run of complete columns in x (columns past the matrix count as complete)
+    auto complete = [&](const uint64_t (&x)[NV * W]) -> int {
+      bool ok = true;
 #pragma unroll
-    for (int q = 0; q < NV * W; ++q) ok = ok && (uint32_t)(x[q] >> 32) == epoch;
-    ok = ok || !real;
-    const uint64_t okm = __ballot(ok);
-    const int run = ~okm == 0 ? 64 : __builtin_ctzll(~okm);
-    const int take = (int)(run < n - u ? run : n - u);
-    if (take == 0) {
+      for (int q = 0; q < NV * W; ++q) ok = ok && (uint32_t)(x[q] >> 32) == epoch;
+      ok = ok || !real;
+      const uint64_t okm = __ballot(ok);
+      const int run = ~okm == 0 ? 64 : __builtin_ctzll(~okm);
+      return (int)(run < n - u ? run : n - u);
+    };
+    // false when the wait has to give up
+    auto pause = [&]() -> bool {
       if (polls == 0) t0 = __builtin_amdgcn_s_memrealtime();
       __builtin_amdgcn_s_sleep(1);
       if ((++polls & 63u) == 0u) {
@@ -194,110 +183,349 @@ __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl,
           return false;
         }
       }
-      continue;
+      return true;
+    };
+    auto deliver = [&](const uint64_t (&x)[NV * W], int take) {
+      if (lane < take) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          uint32_t w[W];
+#pragma unroll
+          for (int q = 0; q < W; ++q) w[q] = (uint32_t)x[v * W + q];
+          ring[v * kRing + (int)((u + lane) & (kRing - 1))] = E::from_words(w);
+        }
+      }
+      u += take;
+      lds_publish(&sh.avail, (uint32_t)u);
+    };
+    issue(xa);
+    for (;;) {
+      issue(xb);
+      int take = complete(xa);
+      if (take > 0) {
+        deliver(xa, take);
+        break;
+      }
+      if (!pause()) return false;
+      issue(xa);
+      take = complete(xb);
+      if (take > 0) {
+        deliver(xb, take);
+        break;
+      }
+      if (!pause()) return false;
     }
     polls = 0;
-    if (lane < take) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        uint32_t w[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) w[q] = (uint32_t)x[v * W + q];
-        ring[v * kRing + (int)((u + lane) & (kRing - 1))] = E::from_words(w);
-      }
-    }
-    u += take;
-    lds_publish(&sh.avail, (uint32_t)u);
   }
+  // the kFill columns after the last one hold 'fill', so that the consumer's vector reads of
+  // them need no selects; they count as delivered once written
+  if (n + kFill - kRing > 0 && !lds_wait_ge(&sh.used, (uint32_t)(n + kFill - kRing), &sh.abort, ctl, waited))
+    return false;
+  for (int c = lane; c < kFill; c += 64) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ring[v * kRing + (int)((n + c) & (kRing - 1))] = fill[v];
+  }
+  lds_publish(&sh.avail, (uint32_t)(n + kFill));
   return true;
 }
 
 // ---------------------------------------------------------------------------------------
 // Forward.
 
-// 4-step groups of inputs in flight: the chain takes tens of nanoseconds per step, so the
-// loads must be issued a memory latency (1-2 us under load) ahead of their use.
-template <typename T>
-struct SoftPF {
-  static constexpr int PD = sizeof(T) == 4 ? 8 : 4;
-};
-
-// Handoff values of 4 consecutive consumer columns k0 .. k0+3 from the ring (vector NV-th
-// plane), or 'fill' past the last column.
-template <typename T>
-__device__ __forceinline__ Vec4<T> ring4(const T* ring, int64_t k0, int64_t n, T fill) {
-  // k0 is a multiple of 4: four whole columns are one aligned vector of the ring
-  if (k0 + 4 <= n) return *reinterpret_cast<const Vec4<T>*>(ring + (int)(k0 & (kRing - 1)));
-  Vec4<T> v;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) v.v[q] = k0 + q < n ? ring[(int)((k0 + q) & (kRing - 1))] : fill;
-  return v;
-}
-
 // ---------------------------------------------------------------------------------------
 // Adjoint.
 
+// Adjoint: a band pipeline of six waves per 64-row band, bands claimed bottom-up.
+//
+// Lane r owns band row r and at step t handles column n + 62 - r - t (the bottom row leads,
+// right to left).  D and C are staged in two skewed LDS rings: element (row r, column c) sits
+// at slot (n + 62 - r - c) mod RING, the step that uses it, so at step t every lane touches
+// slot t and four steps are one aligned 16-byte LDS read per ring.  Slots [4j, 4j+4) of a row
+// hold four consecutive columns in descending order, one (4-byte aligned) 16-byte global
+// transfer with its elements reversed.  The compute wave writes A over C in place; a storer
+// wave writes it back as gC.
+//   wave 0  compute   per 4 steps: the D and C vectors (read one group ahead), the band
+//                     below's (A, V) pairs from the handoff ring, 3 x 4 weights, the A vector
+//                     back to LDS, and row 0's (A, V) into the out ring;
+//   wave 1  loader    sub-chunks of D (SUB slots of every row), two in flight in registers;
+//   wave 2  loader    the same for C;
+//   wave 3  poller    the band below's row-0 (A, V) words into the handoff ring;
+//   wave 4  storer    each finished sub-chunk's A back to gC;
+//   wave 5  publisher this band's row-0 (A, V) words for the band above.
+// With an upstream gD the compute wave reads it straight from global memory along its own
+// row, issued PD groups ahead (a third ring does not fit in LDS).
 template <typename T>
-__device__ __forceinline__ bool soft_bwd_compute(T* ring, T* pub, SoftShared& sh, const SoftArgs& a, int band) {
+struct SbCfg {
+  static constexpr int RING = sizeof(T) == 4 ? 256 : 128;   // slots per row (about 64 KiB a ring)
+  static constexpr int SUB = sizeof(T) == 4 ? 64 : 32;      // slots per sub-chunk
+  static constexpr int PITCH = RING + 16 / (int)sizeof(T);  // row pitch 16 mod 256 bytes
+  static constexpr int MASK = RING - 1;
+  static constexpr int CPR = SUB / 4;                       // 4-slot chunks per row of a sub-chunk
+  static constexpr int RPV = 64 / CPR;                      // rows one vector index spans across the wave
+  static constexpr int NV = CPR;                            // vectors per lane per sub-chunk
+  static constexpr int GPS = SUB / 4;                       // 4-step groups per sub-chunk
+  static constexpr int NSUB = RING / SUB;                   // sub-chunks the ring holds
+  static constexpr int PF = 1;                              // sub-chunks a loader keeps in flight
+  static constexpr int PD = sizeof(T) == 4 ? 8 : 2;         // gD groups in flight (divides GPS)
+  static_assert(NSUB >= 4 && GPS % PD == 0, "bad tiling");
+};
+
+constexpr int kSbThreads = 6 * 64;
+
+// Returns x unchanged, but hides its value from the optimiser at this point: each role
+// launders the kernel-wide sizes it uses, or the compiler hoists every role's address
+// arithmetic out of the band loop and keeps all of it live across all roles.
+template <typename V>
+__device__ __forceinline__ V opaque(V x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+// The same for a per-lane value.
+__device__ __forceinline__ int opaque_lane() {
+  int x = (int)(threadIdx.x & 63);
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, uint32_t off, const Vec4<T>& v) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, off, 0, 0);
+  } else {
+    struct Hf { v4i lo, hi; };
+    const Hf h = __builtin_bit_cast(Hf, v);
+    __builtin_amdgcn_raw_buffer_store_b128(h.lo, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(h.hi, r, off + 16, 0, 0);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ Vec4<T> reversed(const Vec4<T>& v) {
+  Vec4<T> o;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o.v[e] = v.v[3 - e];
+  return o;
+}
+
+// Vector k of a lane in sub-chunk s: row i, slots t0 .. t0+3, which hold columns c_lo+3 down
+// to c_lo.  32-bit arithmetic: a band spans less than 2^30 bytes (the leading-dimension
+// limit of the entry points), so every element offset within it fits.
+template <typename T>
+struct SbVec {
+  int i;
+  int t0;
+  int c_lo;
+  __device__ __forceinline__ SbVec(int lane, int k, int s, int n) {
+    using K = SbCfg<T>;
+    i = K::RPV * k + lane / K::CPR;
+    t0 = K::SUB * s + 4 * (lane % K::CPR);
+    c_lo = n + 59 - i - t0;
+  }
+  __device__ __forceinline__ int lds(int pitch) const { return i * pitch + (t0 & SbCfg<T>::MASK); }
+};
+
+template <typename T>
+__device__ __forceinline__ T load1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+}
+
+// Four consecutive elements from element offset e of a resource.  Offsets below 0 (columns
+// below 0, near the left edge only) read element 0 instead: those positions hold no data
+// that a real cell uses.
+template <typename T>
+__device__ __forceinline__ Vec4<T> sb_load4(__amdgpu_buffer_rsrc_t r, int e) {
+  if (__all(e >= 0)) return load4<T>(r, (uint32_t)e * (uint32_t)sizeof(T));
+  Vec4<T> v;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v.v[q] = load1<T>(r, (uint32_t)(e + q > 0 ? e + q : 0) * (uint32_t)sizeof(T));
+  return v;
+}
+
+// Loads sub-chunk s of one input.  Columns past the row's end read the next row (or zeros
+// past the band's end), columns below 0 the row before (or nothing, before the band's
+// start); none of them reaches a real cell.
+template <typename T>
+__device__ __forceinline__ void sb_load_sub(Vec4<T> (&buf)[SbCfg<T>::NV], __amdgpu_buffer_rsrc_t rsrc, int ld, int n,
+                                            int s, int lane) {
+  using K = SbCfg<T>;
+  __builtin_amdgcn_sched_barrier(0);
+  // an element offset is at least n + 63 - SUB (s+1): below 0 in the last sub-chunks only
+  if (n + 63 >= K::SUB * (s + 1)) {
+#pragma unroll
+    for (int k = 0; k < K::NV; ++k) {
+      const SbVec<T> v(lane, k, s, n);
+      buf[k] = load4<T>(rsrc, (uint32_t)(v.i * ld + v.c_lo) * (uint32_t)sizeof(T));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K::NV; ++k) {
+      const SbVec<T> v(lane, k, s, n);
+      buf[k] = sb_load4<T>(rsrc, v.i * ld + v.c_lo);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// waves 1 and 2: one input into its ring.  Sub-chunk s reuses the slots of sub-chunk
+// s - NSUB, which 'freed' must have released.
+template <typename T>
+__device__ __forceinline__ bool sb_loader(T* P, SoftShared& sh, const SoftArgs& a, const void* src, int64_t ld64,
+                                          int band, int Ks, uint32_t* cnt, const uint32_t* freed) {
+  using K = SbCfg<T>;
+  const int n = (int)opaque(a.n);
+  const int ld = (int)opaque(ld64);
+  const int lane = opaque_lane();
+  const int64_t row0 = (int64_t)band * kBand;
+  const int rows = (int)(a.m - row0 < kBand ? a.m - row0 : kBand);
+  const __amdgpu_buffer_rsrc_t rsrc = band_rsrc<T>(src, row0, rows, ld, n);
+  uint64_t waited = 0;
+  Vec4<T> buf[K::PF][K::NV];
+#pragma unroll
+  for (int p = 0; p < K::PF; ++p) sb_load_sub<T>(buf[p], rsrc, ld, n, p, lane);
+  for (int s0 = 0; s0 < Ks; s0 += K::PF) {
+#pragma unroll
+    for (int p = 0; p < K::PF; ++p) {
+      const int s = s0 + p;
+      if (s < Ks) {
+        const int older = s - K::NSUB;
+        if (older >= 0 && !lds_wait_ge<false>(freed, (uint32_t)(older + 1), &sh.abort, a.ctl, waited)) return false;
+#pragma unroll
+        for (int k = 0; k < K::NV; ++k) {
+          const SbVec<T> v(lane, k, s, n);
+          *reinterpret_cast<Vec4<T>*>(P + v.lds(K::PITCH)) = reversed(buf[p][k]);
+        }
+        lds_signal(cnt, (uint32_t)(s + 1));
+        if (s + K::PF < Ks) sb_load_sub<T>(buf[p], rsrc, ld, n, s + K::PF, lane);
+      }
+    }
+  }
+  return true;
+}
+
+// wave 4: gC from the C ring (which the compute wave overwrote with A).
+template <typename T>
+__device__ __forceinline__ bool sb_store(const T* P, SoftShared& sh, const SoftArgs& a, int band, int Ks) {
+  using K = SbCfg<T>;
+  const int n = (int)opaque(a.n);
+  const int lane = opaque_lane();
+  const int64_t row0 = (int64_t)band * kBand;
+  const int rows = (int)(a.m - row0 < kBand ? a.m - row0 : kBand);
+  const int ldgc = (int)opaque(a.ldgc);
+  const __amdgpu_buffer_rsrc_t ro = band_rsrc<T>(a.gC, row0, rows, ldgc, n);
+  constexpr uint32_t es = sizeof(T);
+  uint64_t waited = 0;
+  for (int s = 0; s < Ks; ++s) {
+    if (!lds_wait_ge(&sh.done, (uint32_t)(s + 1), &sh.abort, a.ctl, waited)) return false;
+    Vec4<T> v[K::NV];
+#pragma unroll
+    for (int k = 0; k < K::NV; ++k) {
+      const SbVec<T> q(lane, k, s, n);
+      v[k] = reversed(*reinterpret_cast<const Vec4<T>*>(P + q.lds(K::PITCH)));
+    }
+    // every row real and every column in [0, n): columns n - SUB(s+1) .. n + 62 - SUB s
+    if (rows == kBand && K::SUB * s >= 63 && K::SUB * (s + 1) <= n) {
+#pragma unroll
+      for (int k = 0; k < K::NV; ++k) {
+        const SbVec<T> q(lane, k, s, n);
+        store4<T>(ro, (uint32_t)(q.i * ldgc + q.c_lo) * es, v[k]);
+      }
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < K::NV; ++k) {
+        const SbVec<T> q(lane, k, s, n);
+        if (q.i >= rows) continue;
+        if (q.c_lo >= 0 && q.c_lo + 4 <= n) {
+          store4<T>(ro, (uint32_t)(q.i * ldgc + q.c_lo) * es, v[k]);
+          continue;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = q.c_lo + e;
+          if (c >= 0 && c < n) store1<T>(ro, (uint32_t)(q.i * ldgc + c) * es, v[k].v[e]);
+        }
+      }
+    }
+    lds_publish(&sh.stored, (uint32_t)(s + 1));
+  }
+  return true;
+}
+
+// Both loader counters in one 8-byte LDS read: sub-chunk s of D and of C is in LDS.
+__device__ __forceinline__ bool sb_loaded(const SoftShared& sh, int s) {
+  const uint64_t w =
+      __hip_atomic_load(reinterpret_cast<const uint64_t*>(&sh.ld[0]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)w);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(w >> 32));
+  return lo >= (uint32_t)(s + 1) && hi >= (uint32_t)(s + 1);  // wave-uniform
+}
+
+// wave 0: the adjoint chain.  BOTTOM: the matrix's last band, whose successors below lie
+// outside (A = 0, V = -inf) and which reads no handoff.
+template <typename T, bool HAS_GD, bool BOTTOM>
+__device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restrict__ Cp, const T* ring, T* pub,
+                                           SoftShared& sh, const SoftArgs& a, int band, int Ks) {
   using E = Elem<T>;
   using M = SoftMath<T>;
-  constexpr int W = E::W;
-  constexpr int PD = SoftPF<T>::PD;
-  const int lane = threadIdx.x & 63;
-  const int64_t m = a.m, n = a.n;
+  using K = SbCfg<T>;
+  constexpr int PD = K::PD;
+  const int lane = opaque_lane();
+  const int64_t m = opaque(a.m), n = opaque(a.n);
   const int64_t row0 = (int64_t)band * kBand;
   const int rows = (int)(m - row0 < kBand ? m - row0 : kBand);
   const int64_t i = row0 + lane;
   const bool live = lane < rows;
-  const auto rc = band_rsrc<T>(a.C, row0, rows, a.ldc, n);
-  const auto rd = band_rsrc<T>(a.Din, row0, rows, a.ldd, n);
-  const auto rg = band_rsrc<T>(a.gD, row0, a.gD ? rows : 0, a.ldgd, n);
-  const auto ro = band_rsrc<T>(a.gC, row0, rows, a.ldgc, n);
-  const bool has_gd = a.gD != nullptr;
   const T kx = (T)a.kx;
-  const bool bottom = band == a.nb - 1;  // no band below: successors below are outside
   const bool pubband = band > 0;  // a band above reads this band's first row
   const bool publish = lane == 0 && pubband;
   const T gs = a.gscore ? *static_cast<const T*>(a.gscore) : E::zero();
   const T NEG = -E::inf();
-  // this lane's column at step t is n - 1 - t + 63 - lane; group g covers steps 4g .. 4g+3,
-  // columns j0 - 3 .. j0 with j0 = n + 62 - lane - 4g, loaded as one 4-column vector
-  const int64_t groups = (n + 63 + 3) / 4;
+  const int64_t groups = (int64_t)Ks * K::GPS;
   // groups [g_lo, g_hi) have every lane's four columns inside the matrix (a full band only):
   // lane 0's highest column n+62-4g <= n-1 needs g >= 16, lane 63's lowest n-4-4g >= 0 needs
   // g <= (n-4)/4
   const int64_t g_lo = rows == kBand ? 16 : groups, g_hi = rows == kBand && n >= 4 ? (n - 4) / 4 + 1 : 0;
-  auto first_col = [&](int64_t g) -> int64_t { return n + 62 - lane - 4 * g - 3; };
-  auto off = [&](int64_t ld, int64_t col) -> uint32_t { return (uint32_t)(((int64_t)lane * ld + col) * sizeof(T)); };
-  Vec4<T> db[PD], cb[PD], gb[PD];
+  __amdgpu_buffer_rsrc_t rg;
+  Vec4<T> gb[PD];
+  int gbase = 0;  // element offset of this lane's column n + 59 - lane (32-bit: see SbVec)
+  if constexpr (HAS_GD) {
+    const int ldgd = (int)opaque(a.ldgd);
+    rg = band_rsrc<T>(a.gD, row0, rows, ldgd, n);
+    gbase = lane * ldgd + (int)n + 59 - lane;
 #pragma unroll
-  for (int k = 0; k < PD; ++k) {
-    db[k] = load4_at<T>(rd, a.ldd, lane, first_col(k));
-    cb[k] = load4_at<T>(rc, a.ldc, lane, first_col(k));
-    if (has_gd) gb[k] = load4_at<T>(rg, a.ldgd, lane, first_col(k));
+    for (int k = 0; k < PD; ++k) gb[k] = sb_load4<T>(rg, gbase - 4 * k);
   }
-  T Ae = E::zero(), Ve = NEG;        // east successor: this lane's previous cell
-  T Aso = E::zero(), Vso = NEG;      // south successor of the previous step (south-east now)
+  T Ae = E::zero(), Ve = NEG;    // east successor: this lane's previous cell
+  T Aso = E::zero(), Vso = NEG;  // south successor of the previous step (south-east now)
   uint64_t waited = 0;
-  // columns of the band below's first row known to be in the ring (wave-uniform)
-  uint32_t have = bottom ? 0xffffffffu : 0u;
+  // Consumer columns of the band below's first row known to be in the handoff ring
+  // (wave-uniform); 'pend' is the counter read issued one group earlier, so that no group
+  // waits for it.  Group g reads the ring's columns 4g .. 4g+3, which past the last column
+  // hold the fill values the poller writes after it (counted as kFill more columns).
+  uint32_t have = 0u, pend = 0u;
+  auto need_of = [&](int64_t g) -> int64_t { return 4 * g + 4 <= n ? 4 * g + 4 : n + kFill; };
   auto avail_for = [&](int64_t g) -> bool {
-    const int64_t need = 4 * g + 4 < n ? 4 * g + 4 : n;
-    if (need <= (int64_t)have) return true;
-    have = lds_load(&sh.avail);
+    const int64_t need = need_of(g);
     if (need <= (int64_t)have) return true;
     uint32_t seen;
     if (!lds_wait_value<true, false>(&sh.avail, (uint32_t)need, &sh.abort, a.ctl, waited, seen)) return false;
-    have = seen;
+    have = (uint32_t)__builtin_amdgcn_readfirstlane((int)seen);
     return true;
   };
-  // the band below's row-0 (A, V) at lane 63's columns n-1-4g-q, consumer order 4g+q
-  Vec4<T> ba, bv;
+  // the band below's row-0 (A, V) at lane 63's columns n-1-4g-q, consumer order 4g+q: one
+  // aligned vector per plane, read unconditionally (a read under a condition would make the
+  // wave wait for it where the paths join)
   auto read_bottom = [&](int64_t g, Vec4<T>& va, Vec4<T>& vv) {
-    va = ring4<T>(ring, 4 * g, n, E::zero());
-    vv = ring4<T>(ring + kRing, 4 * g, n, NEG);
+    const int sl = (int)((4 * g) & (kRing - 1));
+    va = *reinterpret_cast<const Vec4<T>*>(ring + sl);
+    vv = *reinterpret_cast<const Vec4<T>*>(ring + kRing + sl);
   };
-  if (bottom) {
+  Vec4<T> ba, bv;
+  if constexpr (BOTTOM) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       ba.v[q] = E::zero();
@@ -307,43 +535,66 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, T* pub, SoftShared& sh
     if (!avail_for(0)) return false;
     read_bottom(0, ba, bv);
   }
-  for (int64_t g0 = 0; g0 < groups; g0 += PD) {
-    // the batch's out-ring slots must have been published
-    if (pubband && 4 * (g0 + PD) > kPub &&
-        !lds_wait_ge(&sh.pubd, (uint32_t)(4 * (g0 + PD) - kPub), &sh.abort, a.ctl, waited))
-      return false;
-#pragma unroll
-    for (int k = 0; k < PD; ++k) {
-      const int64_t g = g0 + k;
-      if (g < groups) {
-        const Vec4<T> dg = db[k], cg = cb[k];
-        db[k] = load4_at<T>(rd, a.ldd, lane, first_col(g + PD));
-        cb[k] = load4_at<T>(rc, a.ldc, lane, first_col(g + PD));
+  const T* Drow = Dp + lane * K::PITCH;
+  T* Crow = Cp + lane * K::PITCH;
+  auto wait_loaded = [&](int s) -> bool {
+    return lds_wait_until([&] { return sb_loaded(sh, s); }, &sh.abort, a.ctl, waited);
+  };
+  if (!wait_loaded(0)) return false;
+  Vec4<T> dn = *reinterpret_cast<const Vec4<T>*>(Drow), cn = *reinterpret_cast<const Vec4<T>*>(Crow);
+  for (int s = 0; s < Ks; ++s) {
+    for (int64_t g0 = (int64_t)s * K::GPS; g0 < (int64_t)(s + 1) * K::GPS; g0 += PD) {
+      // the batch's out-ring slots must have been published
+      if (pubband && 4 * (g0 + PD) > kPub &&
+          !lds_wait_ge(&sh.pubd, (uint32_t)(4 * (g0 + PD) - kPub), &sh.abort, a.ctl, waited))
+        return false;
+      // one 4-step group; false when a wait has to give up
+      auto group = [&](int k) -> bool {
+        const int64_t g = g0 + k;
+        if constexpr (!BOTTOM) {
+          // The counter read issued a group ago, into a scalar before any of this group's
+          // reads are issued: waiting for it then waits for nothing recent.
+          const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane((int)pend);
+          have = p > have ? p : have;
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        const Vec4<T> dg = dn, cg = cn;
+        // the next group's D and C: in this sub-chunk, or in the next one if already loaded
+        const bool next_sub = (g + 1) % K::GPS == 0;
+        const bool pre = g + 1 < groups && (!next_sub || sb_loaded(sh, s + 1));
+        if (pre) {
+          const int sl = (int)((4 * (g + 1)) & K::MASK);
+          dn = *reinterpret_cast<const Vec4<T>*>(Drow + sl);
+          cn = *reinterpret_cast<const Vec4<T>*>(Crow + sl);
+        }
         Vec4<T> gg;
-        if (has_gd) {
+        if constexpr (HAS_GD) {
           gg = gb[k];
-          gb[k] = load4_at<T>(rg, a.ldgd, lane, first_col(g + PD));
+          gb[k] = sb_load4<T>(rg, gbase - 4 * (int)(g + PD));
         }
+        // the next group's handoff values, valid if the counter read before them covers them
         Vec4<T> na = ba, nv = bv;
-        bool n_ready = bottom;
-        if (!bottom && g + 1 < groups && 4 * g + 8 <= (int64_t)have) {
+        bool n_ready = true;
+        if constexpr (!BOTTOM) {
+          n_ready = need_of(g + 1) <= (int64_t)have;
           read_bottom(g + 1, na, nv);
-          n_ready = true;
+          pend = lds_load(&sh.avail);
+          // keeps later ring reads after this counter read (the LDS performs one wave's
+          // accesses in order)
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
-        const int64_t j0 = n + 62 - lane - 4 * g;
-        // interior group (full band, every lane's columns j0-3 .. j0 inside the matrix, the
-        // last cell not among them): no validity selects, one vector store
+        const int64_t j0 = n + 62 - lane - 4 * g;  // this lane's column at step 4g
         const bool interior = g >= g_lo && g < g_hi;
         Vec4<T> out;
         if (interior) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
-            const T dd = dg.v[3 - q], cc = cg.v[3 - q];
-            T acc = has_gd ? gg.v[3 - q] : E::zero();
-            acc = __builtin_fma(M::exp2_((Vso - dd) * kx), Aso, acc);
-            acc = __builtin_fma(M::exp2_((Vs - dd) * kx), As, acc);
-            acc = __builtin_fma(M::exp2_((Ve - dd) * kx), Ae, acc);
+            const T dd = dg.v[q], cc = cg.v[q];
+            T acc = HAS_GD ? gg.v[3 - q] : E::zero();
+            acc = M::fma_(M::exp2_((Vso - dd) * kx), Aso, acc);
+            acc = M::fma_(M::exp2_((Vs - dd) * kx), As, acc);
+            acc = M::fma_(M::exp2_((Ve - dd) * kx), Ae, acc);
             Aso = As;
             Vso = Vs;
             Ae = acc;
@@ -356,12 +607,12 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, T* pub, SoftShared& sh
             const int64_t j = j0 - q;
             const bool valid = live && j >= 0 && j < n;
             const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
-            const T dd = dg.v[3 - q], cc = cg.v[3 - q];
-            T acc = has_gd ? gg.v[3 - q] : E::zero();
+            const T dd = dg.v[q], cc = cg.v[q];
+            T acc = HAS_GD ? gg.v[3 - q] : E::zero();
             if (i == m - 1 && j == n - 1) acc = acc + gs;
-            acc = __builtin_fma(M::exp2_((Vso - dd) * kx), Aso, acc);
-            acc = __builtin_fma(M::exp2_((Vs - dd) * kx), As, acc);
-            acc = __builtin_fma(M::exp2_((Ve - dd) * kx), Ae, acc);
+            acc = M::fma_(M::exp2_((Vso - dd) * kx), Aso, acc);
+            acc = M::fma_(M::exp2_((Vs - dd) * kx), As, acc);
+            acc = M::fma_(M::exp2_((Ve - dd) * kx), Ae, acc);
             const T vown = dd - cc;
             Aso = As;
             Vso = Vs;
@@ -370,56 +621,53 @@ __device__ __forceinline__ bool soft_bwd_compute(T* ring, T* pub, SoftShared& sh
             out.v[q] = Ae;
           }
         }
-        if (live) {
-          // the group's columns are j0-3 .. j0, out.v[q] at column j0 - q
-          bool whole = false;
-          if constexpr (sizeof(T) == 4) {
-            if (interior || (j0 - 3 >= 0 && j0 < n)) {
-              Vec4<T> asc;
-#pragma unroll
-              for (int q = 0; q < 4; ++q) asc.v[q] = out.v[3 - q];
-              __builtin_amdgcn_raw_buffer_store_b128(
-                  __builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, asc), ro, off(a.ldgc, j0 - 3), 0,
-                  0);
-              whole = true;
-            }
-          }
-          if (!whole) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int64_t j = j0 - q;
-              if (j >= 0 && j < n) store1<T>(ro, off(a.ldgc, j), out.v[q]);
-            }
-          }
-        }
+        *reinterpret_cast<Vec4<T>*>(Crow + ((4 * g) & K::MASK)) = out;
         if (publish) {
           // lane 0's (A, V) of steps 4g .. 4g+3 (columns j0 .. j0-3) to the out ring
           Vec4<T> vs;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) vs.v[q] = dg.v[3 - q] - cg.v[3 - q];
+          for (int q = 0; q < 4; ++q) vs.v[q] = dg.v[q] - cg.v[q];
           *reinterpret_cast<Vec4<T>*>(pub + (int)((4 * g) & (kPub - 1))) = out;
           *reinterpret_cast<Vec4<T>*>(pub + kPub + (int)((4 * g) & (kPub - 1))) = vs;
           lds_signal(&sh.produced, (uint32_t)(4 * g + 4));
         }
-        if (!n_ready && g + 1 < groups) {
-          if (!avail_for(g + 1)) return false;
-          read_bottom(g + 1, na, nv);
+        if constexpr (!BOTTOM) {
+          if (!n_ready && g + 1 < groups) {
+            if (!avail_for(g + 1)) return false;
+            read_bottom(g + 1, na, nv);
+          }
         }
         ba = na;
         bv = nv;
-      }
+        if (!pre && g + 1 < groups) {
+          if (!wait_loaded(s + 1)) return false;
+          const int sl = (int)((4 * (g + 1)) & K::MASK);
+          dn = *reinterpret_cast<const Vec4<T>*>(Drow + sl);
+          cn = *reinterpret_cast<const Vec4<T>*>(Crow + sl);
+        }
+        return true;
+      };
+#pragma unroll
+      for (int k = 0; k < PD; ++k)
+        if (!group(k)) return false;
+      if (!BOTTOM && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * (g0 + PD) < n ? 4 * (g0 + PD) : n));
     }
-    if (!bottom && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * (g0 + PD) < n ? 4 * (g0 + PD) : n));
+    lds_signal(&sh.done, (uint32_t)(s + 1));
   }
   return true;
 }
 
-template <typename T>
-__global__ __launch_bounds__(192) void soft_bwd_kernel(SoftArgs a) {
+template <typename T, bool HAS_GD>
+__global__ __launch_bounds__(kSbThreads, 1) void soft_bwd_kernel(SoftArgs a) {
   using E = Elem<T>;
+  using K = SbCfg<T>;
+  __shared__ Vec4<T> D4[kBand * K::PITCH / 4];
+  __shared__ Vec4<T> C4[kBand * K::PITCH / 4];
   __shared__ alignas(16) T ring[2 * kRing];
   __shared__ alignas(16) T pub[2 * kPub];
   __shared__ SoftShared sh;
+  T* Dp = reinterpret_cast<T*>(D4);
+  T* Cp = reinterpret_cast<T*>(C4);
   Control* ctl = a.ctl;
   const uint32_t epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (threadIdx.x == 0) sh.abort = 0u;
@@ -429,6 +677,10 @@ __global__ __launch_bounds__(192) void soft_bwd_kernel(SoftArgs a) {
       sh.used = 0u;
       sh.produced = 0u;
       sh.pubd = 0u;
+      sh.ld[0] = 0u;
+      sh.ld[1] = 0u;
+      sh.done = 0u;
+      sh.stored = 0u;
     }
     claim_next(ctl, &sh.item, &sh.abort);
     // bands from the bottom up
@@ -436,17 +688,26 @@ __global__ __launch_bounds__(192) void soft_bwd_kernel(SoftArgs a) {
     if ((int)sh.item >= a.nb || sh.abort != 0u) break;
     bool ok = true;
     const int64_t n = a.n;
-    if (threadIdx.x < 64) {
-      ok = soft_bwd_compute<T>(ring, pub, sh, a, band);
-    } else if (threadIdx.x < 128) {
+    const int Ks = (int)((n + 63 + K::SUB - 1) / K::SUB);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform branches below
+    if (wave == 0) {
+      ok = band == a.nb - 1 ? sb_compute<T, HAS_GD, true>(Dp, Cp, ring, pub, sh, a, band, Ks)
+                            : sb_compute<T, HAS_GD, false>(Dp, Cp, ring, pub, sh, a, band, Ks);
+    } else if (wave == 1) {
+      ok = sb_loader<T>(Dp, sh, a, a.Din, a.ldd, band, Ks, &sh.ld[0], &sh.done);
+    } else if (wave == 2) {
+      ok = sb_loader<T>(Cp, sh, a, a.C, a.ldc, band, Ks, &sh.ld[1], &sh.stored);
+    } else if (wave == 3) {
       // consumer column k is matrix column n-1-k of the band below's first row
       if (band < a.nb - 1)
-        ok = poll_ring<T, 2>(ring, sh, ctl, n, epoch, [&](int64_t k) {
+        ok = poll_ring<T, 2>(ring, sh, ctl, n, epoch, {E::zero(), -E::inf()}, [&](int64_t k) {
           return a.bnd + ((int64_t)band * n + (n - 1 - k)) * 2 * E::W;
         });
+    } else if (wave == 4) {
+      ok = sb_store<T>(Cp, sh, a, band, Ks);
     } else if (band > 0) {
       // the first row (lane 0 handles column n + 62 - s at step s) for the band above
-      const uint32_t total = (uint32_t)(4 * ((n + 63 + 3) / 4));
+      const uint32_t total = (uint32_t)(4 * (int64_t)Ks * K::GPS);
       ok = publish_ring<T, 2>(pub, sh, ctl, n, total, epoch, [n](int64_t st) { return n + 62 - st; },
                               [&](int64_t c, int v) { return a.bnd + ((int64_t)(band - 1) * n + c) * 2 * E::W + v * E::W; });
     }
@@ -459,12 +720,16 @@ __global__ __launch_bounds__(192) void soft_bwd_kernel(SoftArgs a) {
 }  // namespace
 
 hipError_t launch_soft_backward(int dtype, const SoftArgs& a, int grid, hipStream_t s) {
-  if (dtype == 0)
-    hipLaunchKernelGGL(soft_bwd_kernel<float>, dim3(grid), dim3(192), 0, s, a);
-  else if (dtype == 1)
-    hipLaunchKernelGGL(soft_bwd_kernel<double>, dim3(grid), dim3(192), 0, s, a);
-  else
+  const bool gd = a.gD != nullptr;
+  if (dtype == 0) {
+    if (gd) hipLaunchKernelGGL((soft_bwd_kernel<float, true>), dim3(grid), dim3(kSbThreads), 0, s, a);
+    else hipLaunchKernelGGL((soft_bwd_kernel<float, false>), dim3(grid), dim3(kSbThreads), 0, s, a);
+  } else if (dtype == 1) {
+    if (gd) hipLaunchKernelGGL((soft_bwd_kernel<double, true>), dim3(grid), dim3(kSbThreads), 0, s, a);
+    else hipLaunchKernelGGL((soft_bwd_kernel<double, false>), dim3(grid), dim3(kSbThreads), 0, s, a);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
