@@ -182,6 +182,63 @@ def test_more_bands_than_workgroups(oracle_mod):
     assert err <= bar and fnw <= 1e-4 and fel <= 1e-4
 
 
+def test_bench_matrix_full_size(oracle_mod):
+    """The bench's 16384 x 16384 soft-min workload (normal(0,1) clipped to [-4, 4], seed 2,
+    gamma = 1), in the bench's launch configuration.
+
+    float64: the adjoint of the score against its closed form.  The gradient of the score
+    with respect to C[i][j] is the Gibbs probability that a path passes through (i, j),
+    exp((score - R[i][j] - Q[i][j] + C[i][j]) / gamma), where R is the forward table and Q
+    the same recurrence run from the far corner (the oracle's forward on the matrix reversed
+    in both axes).  Two oracle sweeps pin every one of the 2.7e8 gradient entries, relative,
+    to the float64 bar of the other adjoint tests.
+    float32: the table's top-left 2048 x 2048 block against the float64 oracle (D[i][j]
+    depends on C[:i+1, :j+1] only), and properties of the adjoint that hold at any size:
+    every entry finite and non-negative (a sum of products of non-negative weights) and the
+    last cell exactly g_score.  (The first cell, which every path visits, is 1 in exact
+    arithmetic; its float32 value is printed, not held to a bar: with tables of 4e4 the
+    float32 bar of the other adjoint tests exceeds 1 at this size.)"""
+    m = n = 16384
+    gamma = 1.0
+    C = inputs.normal_clipped(m, n, seed=2)
+    Cd = C.to(DEV)
+    D32, s32 = wf.soft_forward(Cd, gamma)
+    g32 = wf.soft_backward(Cd, D32, gamma, g_score=torch.tensor(1.0))
+    blk = C[:2048, :2048].numpy().astype(np.float64)
+    want_blk = oracle_mod.soft_forward(blk, gamma)
+    el, nw = grad_err(D32[:2048, :2048].cpu().numpy(), want_blk, cut=1e-2)
+    assert bool(torch.isfinite(g32).all()) and float(g32.min()) >= 0.0
+    assert float(g32[-1, -1]) == 1.0
+    del D32
+
+    C64 = C.numpy().astype(np.float64)
+    del C
+    R = oracle_mod.soft_forward(C64, gamma)
+    Q = oracle_mod.soft_forward(np.ascontiguousarray(C64[::-1, ::-1]), gamma)[::-1, ::-1]
+    Dmax = float(max(np.abs(R).max(), np.abs(Q).max()))
+    first = float(g32[0, 0])
+    del g32
+    print(f"soft 16384^2 f32: table block normwise {nw:.2e}, elementwise {el:.2e}; gC[0][0] = {first:.6f}, "
+          f"max|D| {Dmax:.3e}")
+    assert nw <= 1e-4 and el <= 1e-4
+
+    Cd64 = torch.from_numpy(C64).to(DEV)
+    D64, s64 = wf.soft_forward(Cd64, gamma)
+    g64 = wf.soft_backward(Cd64, D64, gamma, g_score=torch.tensor(1.0, dtype=torch.float64)).cpu().numpy()
+    del D64, Cd64
+    score = float(R[-1, -1])
+    P = np.exp((score - R - Q + C64) / gamma)
+    del R, Q
+    big = P >= 1e-200
+    rel = float(np.max(np.abs(g64[big] - P[big]) / P[big]))
+    tiny = float(np.max(np.abs(g64[~big]))) if (~big).any() else 0.0
+    bar = f64_grad_bar(m, n, Dmax, gamma)
+    print(f"soft 16384^2 f64 adjoint vs closed form: max rel err {rel:.2e} over {int(big.sum())} entries "
+          f"(bar {bar:.2e}); score {float(s64):.6f} vs oracle {score:.6f}")
+    assert rel <= bar and tiny <= 1e-190
+    assert abs(float(s64) - score) <= 1e-10 * abs(score)
+
+
 def test_finite_differences_f64():
     """Central differences (h = 1e-3) of the device's float64 score on 32 cells: the 16
     cells of largest gradient and 16 uniform ones (seeded).  The truncation error is about
