@@ -710,7 +710,7 @@ int wf_soft_backward(int dtype, int64_t m, int64_t n, double gamma, const void* 
   if (hipGetDevice(&dev) != hipSuccess) return WF_E_DEVICE;
   DeviceWs* ws = nullptr;
   rc = ensure_ws_on(dev, static_cast<hipStream_t>(stream),
-                    (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * 2 * words_per_elem(dtype), &ws);
+                    (size_t)(nb > 1 ? nb - 1 : 1) * (size_t)n * 3 * words_per_elem(dtype), &ws);
   if (rc != WF_OK) return rc;
   SoftArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -727,7 +727,6 @@ int wf_soft_backward(int dtype, int64_t m, int64_t n, double gamma, const void* 
   a.n = n;
   a.nb = (int32_t)nb;
   a.kx = 1.0 / (gamma * std::log(2.0));
-  a.gl = gamma * std::log(2.0);
   a.ctl = ws->ctl;
   a.bnd = ws->bnd;
   const int grid = (int)std::min<int64_t>(nb, 4 * (int64_t)ws->num_cus);

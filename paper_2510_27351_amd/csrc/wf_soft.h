@@ -6,14 +6,12 @@
 
 namespace wf {
 
-// Arguments of the smooth (soft-min) sweeps: the forward writes D (and the score) from C;
-// the adjoint reads C and the forward's D (Din) and writes gC.  kx = log2(e) / gamma and
-// gl = gamma ln 2 (the soft minimum in base-2 exponentials and logarithms).
+// Arguments of the smooth (soft-min) adjoint: it reads C and the forward's D (Din) and
+// writes gC.  (The forward takes the min-plus forward's FwdArgs.)  kx = log2(e) / gamma (the
+// weights as base-2 exponentials).
 struct SoftArgs {
   const void* C;
   const void* Din;
-  void* D;
-  void* score;
   const void* gD;       // may be null (zero)
   const void* gscore;   // may be null (zero)
   void* gC;
@@ -21,9 +19,9 @@ struct SoftArgs {
   int64_t m, n;
   int32_t nb;           // 64-row bands
   int32_t pad;
-  double kx, gl;
+  double kx;
   Control* ctl;
-  uint64_t* bnd;        // forward: (nb-1) * n * W words; adjoint: twice that, (A, V) pairs
+  uint64_t* bnd;        // adjoint: (nb-1) * n * 3 * W words, (A, D, C) per column
 };
 hipError_t launch_soft_backward(int dtype, const SoftArgs& a, int grid, hipStream_t s);
 // The soft-min forward runs in the min-plus forward's band pipeline (wf_fwd.hip) with the

@@ -8,25 +8,24 @@
 //     A[i][j] = gD[i][j] + [last] gscore + w(i+1,j+1) A[i+1][j+1] + w(i+1,j) A[i+1][j]
 //             + w(i,j+1) A[i][j+1],       w(succ) = 2^((V(succ) - D[i][j]) log2e / gamma),
 // with V(succ) = D(succ) - C(succ) the successor's soft minimum, so the weight is the
-// derivative of the successor's soft minimum with respect to D[i][j].  gC = A.
+// derivative of the successor's soft minimum with respect to D[i][j].  gC = A.  The
+// exponent is evaluated as (D(succ) - D[i][j]) log2e/gamma - C(succ) log2e/gamma, one fused
+// multiply-add after the difference of two neighbouring table values, which is exact in
+// floating point, so the weight's error is that of numbers of the size of C, not of the
+// table.  (Forming V first would round it at the
+// table's magnitude, and along a path of L cells those roundings add up: at 16384 x 16384
+// in float32 that made the first cell's gradient 8% off.)
 //
 // The forward runs in the min-plus forward's band pipeline (wf_fwd.hip) with the soft-min
-// cell in place of the minimum; this file holds the adjoint.  It is a persistent band
-// pipeline in a lighter form: a workgroup of three waves per 64-row band, claimed bottom-up.
-// The compute wave runs the skewed wavefront (lane r owns band row r; at step t it handles
-// column n - 1 - t + 63 - r), taking the lane-shifted neighbour values through DPP and
-// reading its inputs straight from global memory as 16-byte range-checked buffer loads of
-// four consecutive columns, issued two 4-step groups ahead.  The band's first row goes to
-// the band above as epoch-tagged 64-bit (A, V) word pairs: the compute wave writes it to an
-// LDS out ring and a publisher wave stores it; a poller wave reads the band below's words
-// into an LDS ring that the compute wave reads.  Every wait is bounded.
+// cell in place of the minimum; this file holds the adjoint, a band pipeline of six waves
+// per 64-row band (described with its kernel below).  Every wait is bounded.
 #include "wf_common.h"
 #include "wf_soft.h"
 
 namespace wf {
 namespace {
 
-constexpr int kRing = 1024;  // handoff ring: columns
+constexpr int kRing = 512;   // handoff ring: columns
 constexpr int kFill = 128;   // fill columns after the last one (at least the groups' overhang)
 
 // Four consecutive columns of one row, as one (float) or two (double) 16-byte transfers.
@@ -245,13 +244,14 @@ __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl,
 // transfer with its elements reversed.  The compute wave writes A over C in place; a storer
 // wave writes it back as gC.
 //   wave 0  compute   per 4 steps: the D and C vectors (read one group ahead), the band
-//                     below's (A, V) pairs from the handoff ring, 3 x 4 weights, the A vector
-//                     back to LDS, and row 0's (A, V) into the out ring;
+//                     below's (A, D, C log2e/gamma) from the handoff ring, 3 x 4 weights,
+//                     the A vector back to LDS, and row 0's (A, D, C log2e/gamma) into the
+//                     out ring;
 //   wave 1  loader    sub-chunks of D (SUB slots of every row), two in flight in registers;
 //   wave 2  loader    the same for C;
-//   wave 3  poller    the band below's row-0 (A, V) words into the handoff ring;
+//   wave 3  poller    the band below's row-0 (A, D, C) words into the handoff ring;
 //   wave 4  storer    each finished sub-chunk's A back to gC;
-//   wave 5  publisher this band's row-0 (A, V) words for the band above.
+//   wave 5  publisher this band's row-0 (A, D, C) words for the band above.
 // With an upstream gD the compute wave reads it straight from global memory along its own
 // row, issued PD groups ahead (a third ring does not fit in LDS).
 template <typename T>
@@ -435,7 +435,9 @@ __device__ __forceinline__ bool sb_store(const T* P, SoftShared& sh, const SoftA
         store4<T>(ro, (uint32_t)(q.i * ldgc + q.c_lo) * es, v[k]);
       }
     } else {
-#pragma unroll 1
+      // unrolled like the rest: a loop over k would index v at run time and put it in
+      // scratch memory
+#pragma unroll
       for (int k = 0; k < K::NV; ++k) {
         const SbVec<T> q(lane, k, s, n);
         if (q.i >= rows) continue;
@@ -499,8 +501,13 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
 #pragma unroll
     for (int k = 0; k < PD; ++k) gb[k] = sb_load4<T>(rg, gbase - 4 * k);
   }
-  T Ae = E::zero(), Ve = NEG;    // east successor: this lane's previous cell
-  T Aso = E::zero(), Vso = NEG;  // south successor of the previous step (south-east now)
+  // A, D and C log2(e)/gamma of the east successor (this lane's previous cell) and of the
+  // south successor of the previous step (the south-east one now); a weight's exponent is
+  // (D(succ) - D) log2(e)/gamma - C(succ) log2(e)/gamma, one fused multiply-add after an
+  // exact difference.  A successor outside the matrix has A = 0, D = -inf, C = 0: its weight
+  // is exactly 0.
+  T Ae = E::zero(), De = NEG, Ce = E::zero();
+  T Aso = E::zero(), Dso = NEG, Cso = E::zero();
   uint64_t waited = 0;
   // Consumer columns of the band below's first row known to be in the handoff ring
   // (wave-uniform); 'pend' is the counter read issued one group earlier, so that no group
@@ -516,24 +523,26 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
     have = (uint32_t)__builtin_amdgcn_readfirstlane((int)seen);
     return true;
   };
-  // the band below's row-0 (A, V) at lane 63's columns n-1-4g-q, consumer order 4g+q: one
+  // the band below's row-0 (A, D, C) at lane 63's columns n-1-4g-q, consumer order 4g+q: one
   // aligned vector per plane, read unconditionally (a read under a condition would make the
   // wave wait for it where the paths join)
-  auto read_bottom = [&](int64_t g, Vec4<T>& va, Vec4<T>& vv) {
+  auto read_bottom = [&](int64_t g, Vec4<T>& va, Vec4<T>& vd, Vec4<T>& vc) {
     const int sl = (int)((4 * g) & (kRing - 1));
     va = *reinterpret_cast<const Vec4<T>*>(ring + sl);
-    vv = *reinterpret_cast<const Vec4<T>*>(ring + kRing + sl);
+    vd = *reinterpret_cast<const Vec4<T>*>(ring + kRing + sl);
+    vc = *reinterpret_cast<const Vec4<T>*>(ring + 2 * kRing + sl);
   };
-  Vec4<T> ba, bv;
+  Vec4<T> ba, bd, bc;
   if constexpr (BOTTOM) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       ba.v[q] = E::zero();
-      bv.v[q] = NEG;
+      bd.v[q] = NEG;
+      bc.v[q] = E::zero();
     }
   } else {
     if (!avail_for(0)) return false;
-    read_bottom(0, ba, bv);
+    read_bottom(0, ba, bd, bc);
   }
   const T* Drow = Dp + lane * K::PITCH;
   T* Crow = Cp + lane * K::PITCH;
@@ -558,7 +567,10 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
           have = p > have ? p : have;
           __builtin_amdgcn_sched_barrier(0);
         }
-        const Vec4<T> dg = dn, cg = cn;
+        const Vec4<T> dg = dn;
+        Vec4<T> cg;  // C log2(e)/gamma
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cg.v[q] = cn.v[q] * kx;
         // the next group's D and C: in this sub-chunk, or in the next one if already loaded
         const bool next_sub = (g + 1) % K::GPS == 0;
         const bool pre = g + 1 < groups && (!next_sub || sb_loaded(sh, s + 1));
@@ -573,11 +585,11 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
           gb[k] = sb_load4<T>(rg, gbase - 4 * (int)(g + PD));
         }
         // the next group's handoff values, valid if the counter read before them covers them
-        Vec4<T> na = ba, nv = bv;
+        Vec4<T> na = ba, nd = bd, nc = bc;
         bool n_ready = true;
         if constexpr (!BOTTOM) {
           n_ready = need_of(g + 1) <= (int64_t)have;
-          read_bottom(g + 1, na, nv);
+          read_bottom(g + 1, na, nd, nc);
           pend = lds_load(&sh.avail);
           // keeps later ring reads after this counter read (the LDS performs one wave's
           // accesses in order)
@@ -589,16 +601,18 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
         if (interior) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
+            const T As = shl1_(Ae, ba.v[q]), Ds = shl1_(De, bd.v[q]), Cs = shl1_(Ce, bc.v[q]);
             const T dd = dg.v[q], cc = cg.v[q];
             T acc = HAS_GD ? gg.v[3 - q] : E::zero();
-            acc = M::fma_(M::exp2_((Vso - dd) * kx), Aso, acc);
-            acc = M::fma_(M::exp2_((Vs - dd) * kx), As, acc);
-            acc = M::fma_(M::exp2_((Ve - dd) * kx), Ae, acc);
+            acc = M::fma_(M::exp2_(M::fma_(Dso - dd, kx, -Cso)), Aso, acc);
+            acc = M::fma_(M::exp2_(M::fma_(Ds - dd, kx, -Cs)), As, acc);
+            acc = M::fma_(M::exp2_(M::fma_(De - dd, kx, -Ce)), Ae, acc);
             Aso = As;
-            Vso = Vs;
+            Dso = Ds;
+            Cso = Cs;
             Ae = acc;
-            Ve = dd - cc;
+            De = dd;
+            Ce = cc;
             out.v[q] = acc;
           }
         } else {
@@ -606,39 +620,40 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
           for (int q = 0; q < 4; ++q) {
             const int64_t j = j0 - q;
             const bool valid = live && j >= 0 && j < n;
-            const T As = shl1_(Ae, ba.v[q]), Vs = shl1_(Ve, bv.v[q]);
+            const T As = shl1_(Ae, ba.v[q]), Ds = shl1_(De, bd.v[q]), Cs = shl1_(Ce, bc.v[q]);
             const T dd = dg.v[q], cc = cg.v[q];
             T acc = HAS_GD ? gg.v[3 - q] : E::zero();
             if (i == m - 1 && j == n - 1) acc = acc + gs;
-            acc = M::fma_(M::exp2_((Vso - dd) * kx), Aso, acc);
-            acc = M::fma_(M::exp2_((Vs - dd) * kx), As, acc);
-            acc = M::fma_(M::exp2_((Ve - dd) * kx), Ae, acc);
-            const T vown = dd - cc;
+            acc = M::fma_(M::exp2_(M::fma_(Dso - dd, kx, -Cso)), Aso, acc);
+            acc = M::fma_(M::exp2_(M::fma_(Ds - dd, kx, -Cs)), As, acc);
+            acc = M::fma_(M::exp2_(M::fma_(De - dd, kx, -Ce)), Ae, acc);
             Aso = As;
-            Vso = Vs;
+            Dso = Ds;
+            Cso = Cs;
             Ae = valid ? acc : E::zero();
-            Ve = valid ? vown : NEG;
+            De = valid ? dd : NEG;
+            Ce = valid ? cc : E::zero();
             out.v[q] = Ae;
           }
         }
         *reinterpret_cast<Vec4<T>*>(Crow + ((4 * g) & K::MASK)) = out;
         if (publish) {
-          // lane 0's (A, V) of steps 4g .. 4g+3 (columns j0 .. j0-3) to the out ring
-          Vec4<T> vs;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) vs.v[q] = dg.v[q] - cg.v[q];
-          *reinterpret_cast<Vec4<T>*>(pub + (int)((4 * g) & (kPub - 1))) = out;
-          *reinterpret_cast<Vec4<T>*>(pub + kPub + (int)((4 * g) & (kPub - 1))) = vs;
+          // lane 0's (A, D, C) of steps 4g .. 4g+3 (columns j0 .. j0-3) to the out ring
+          const int ps = (int)((4 * g) & (kPub - 1));
+          *reinterpret_cast<Vec4<T>*>(pub + ps) = out;
+          *reinterpret_cast<Vec4<T>*>(pub + kPub + ps) = dg;
+          *reinterpret_cast<Vec4<T>*>(pub + 2 * kPub + ps) = cg;
           lds_signal(&sh.produced, (uint32_t)(4 * g + 4));
         }
         if constexpr (!BOTTOM) {
           if (!n_ready && g + 1 < groups) {
             if (!avail_for(g + 1)) return false;
-            read_bottom(g + 1, na, nv);
+            read_bottom(g + 1, na, nd, nc);
           }
         }
         ba = na;
-        bv = nv;
+        bd = nd;
+        bc = nc;
         if (!pre && g + 1 < groups) {
           if (!wait_loaded(s + 1)) return false;
           const int sl = (int)((4 * (g + 1)) & K::MASK);
@@ -663,8 +678,8 @@ __global__ __launch_bounds__(kSbThreads, 1) void soft_bwd_kernel(SoftArgs a) {
   using K = SbCfg<T>;
   __shared__ Vec4<T> D4[kBand * K::PITCH / 4];
   __shared__ Vec4<T> C4[kBand * K::PITCH / 4];
-  __shared__ alignas(16) T ring[2 * kRing];
-  __shared__ alignas(16) T pub[2 * kPub];
+  __shared__ alignas(16) T ring[3 * kRing];
+  __shared__ alignas(16) T pub[3 * kPub];
   __shared__ SoftShared sh;
   T* Dp = reinterpret_cast<T*>(D4);
   T* Cp = reinterpret_cast<T*>(C4);
@@ -700,16 +715,16 @@ __global__ __launch_bounds__(kSbThreads, 1) void soft_bwd_kernel(SoftArgs a) {
     } else if (wave == 3) {
       // consumer column k is matrix column n-1-k of the band below's first row
       if (band < a.nb - 1)
-        ok = poll_ring<T, 2>(ring, sh, ctl, n, epoch, {E::zero(), -E::inf()}, [&](int64_t k) {
-          return a.bnd + ((int64_t)band * n + (n - 1 - k)) * 2 * E::W;
+        ok = poll_ring<T, 3>(ring, sh, ctl, n, epoch, {E::zero(), -E::inf(), E::zero()}, [&](int64_t k) {
+          return a.bnd + ((int64_t)band * n + (n - 1 - k)) * 3 * E::W;
         });
     } else if (wave == 4) {
       ok = sb_store<T>(Cp, sh, a, band, Ks);
     } else if (band > 0) {
       // the first row (lane 0 handles column n + 62 - s at step s) for the band above
       const uint32_t total = (uint32_t)(4 * (int64_t)Ks * K::GPS);
-      ok = publish_ring<T, 2>(pub, sh, ctl, n, total, epoch, [n](int64_t st) { return n + 62 - st; },
-                              [&](int64_t c, int v) { return a.bnd + ((int64_t)(band - 1) * n + c) * 2 * E::W + v * E::W; });
+      ok = publish_ring<T, 3>(pub, sh, ctl, n, total, epoch, [n](int64_t st) { return n + 62 - st; },
+                              [&](int64_t c, int v) { return a.bnd + ((int64_t)(band - 1) * n + c) * 3 * E::W + v * E::W; });
     }
     if (!ok) sh.abort = 1u;
     __syncthreads();

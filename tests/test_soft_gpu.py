@@ -196,8 +196,8 @@ def test_bench_matrix_full_size(oracle_mod):
     depends on C[:i+1, :j+1] only), and properties of the adjoint that hold at any size:
     every entry finite and non-negative (a sum of products of non-negative weights) and the
     last cell exactly g_score.  (The first cell, which every path visits, is 1 in exact
-    arithmetic; its float32 value is printed, not held to a bar: with tables of 4e4 the
-    float32 bar of the other adjoint tests exceeds 1 at this size.)"""
+    arithmetic; its float32 value, 0.9992, is printed, not held to a bar: with tables of 4e4
+    the float32 bar of the other adjoint tests exceeds 1 at this size.)"""
     m = n = 16384
     gamma = 1.0
     C = inputs.normal_clipped(m, n, seed=2)
