@@ -136,8 +136,9 @@ __device__ __forceinline__ bool publish_ring(const T* pub, SoftShared& sh, Contr
 // ---------------------------------------------------------------------------------------
 // The poller: fetches the producer band's tagged words, 64 columns per pass from the first
 // one not yet handed over, and hands over the leading run of complete columns.  NV values
-// per column (1 forward, 2 backward), each of W payload words; 'word_at(k)' is the address
-// of the first word of consumer column k.
+// per column (the adjoint's A, D and scaled C), each of W payload words; 'word_at(k)' is the
+// address of the first word of consumer column k.  After the last column it writes 'fill'
+// into the next kFill columns of the ring and counts them as delivered.
 template <typename T, int NV, typename WordAt>
 __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl, int64_t n, uint32_t epoch,
                                           const T (&fill)[NV], WordAt word_at) {
@@ -229,11 +230,6 @@ __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl,
 }
 
 // ---------------------------------------------------------------------------------------
-// Forward.
-
-// ---------------------------------------------------------------------------------------
-// Adjoint.
-
 // Adjoint: a band pipeline of six waves per 64-row band, bands claimed bottom-up.
 //
 // Lane r owns band row r and at step t handles column n + 62 - r - t (the bottom row leads,
@@ -247,11 +243,11 @@ __device__ __forceinline__ bool poll_ring(T* ring, SoftShared& sh, Control* ctl,
 //                     below's (A, D, C log2e/gamma) from the handoff ring, 3 x 4 weights,
 //                     the A vector back to LDS, and row 0's (A, D, C log2e/gamma) into the
 //                     out ring;
-//   wave 1  loader    sub-chunks of D (SUB slots of every row), two in flight in registers;
+//   wave 1  loader    sub-chunks of D (SUB slots of every row), one in flight in registers;
 //   wave 2  loader    the same for C;
-//   wave 3  poller    the band below's row-0 (A, D, C) words into the handoff ring;
+//   wave 3  poller    the band below's row-0 (A, D, C log2e/gamma) words into the handoff ring;
 //   wave 4  storer    each finished sub-chunk's A back to gC;
-//   wave 5  publisher this band's row-0 (A, D, C) words for the band above.
+//   wave 5  publisher this band's row-0 (A, D, C log2e/gamma) words for the band above.
 // With an upstream gD the compute wave reads it straight from global memory along its own
 // row, issued PD groups ahead (a third ring does not fit in LDS).
 template <typename T>
