@@ -475,8 +475,9 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
   const int64_t m = opaque(a.m), n = opaque(a.n);
   const int64_t row0 = (int64_t)band * kBand;
   const int rows = (int)(m - row0 < kBand ? m - row0 : kBand);
-  const int64_t i = row0 + lane;
   const bool live = lane < rows;
+  const int n32 = (int)n;
+  const bool score_lane = lane == rows - 1;  // in the last band: the matrix's last row
   const T kx = (T)a.kx;
   const bool pubband = band > 0;  // a band above reads this band's first row
   const bool publish = lane == 0 && pubband;
@@ -591,7 +592,9 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
           // accesses in order)
           __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
-        const int64_t j0 = n + 62 - lane - 4 * g;  // this lane's column at step 4g
+        // this lane's column at step 4g (32-bit: n < 2^31, and the edge path below runs in
+        // every band's first and last groups, on the critical path of the band below's start)
+        const int j0 = n32 + 62 - lane - 4 * (int)g;
         const bool interior = g >= g_lo && g < g_hi;
         Vec4<T> out;
         if (interior) {
@@ -614,12 +617,15 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
         } else {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int64_t j = j0 - q;
-            const bool valid = live && j >= 0 && j < n;
+            const int j = j0 - q;
+            const bool valid = live && (uint32_t)j < (uint32_t)n32;
             const T As = shl1_(Ae, ba.v[q]), Ds = shl1_(De, bd.v[q]), Cs = shl1_(Ce, bc.v[q]);
             const T dd = dg.v[q], cc = cg.v[q];
             T acc = HAS_GD ? gg.v[3 - q] : E::zero();
-            if (i == m - 1 && j == n - 1) acc = acc + gs;
+            if constexpr (BOTTOM) {
+              // the score's cell: the matrix's last row, last column
+              if (score_lane && j == n32 - 1) acc = acc + gs;
+            }
             acc = M::fma_(M::exp2_(M::fma_(Dso - dd, kx, -Cso)), Aso, acc);
             acc = M::fma_(M::exp2_(M::fma_(Ds - dd, kx, -Cs)), As, acc);
             acc = M::fma_(M::exp2_(M::fma_(De - dd, kx, -Ce)), Ae, acc);
