@@ -267,7 +267,8 @@ def soft_rate(C, steps: int, warmup: int, gamma: float = 1.0, block: int = 2048)
     """The smooth (soft-min) sweep of the benchmark matrix: forward (table and score) and the
     adjoint of the score from the table, each timed with HIP events.  Error: the table's
     top-left block x block against the float64 oracle (D[i][j] depends on C[:i+1, :j+1]
-    only, so the block is exact)."""
+    only, so the block is exact); the adjoint's first and last cells against their exact
+    value 1."""
     import numpy as np
     import torch
 
@@ -304,6 +305,10 @@ def soft_rate(C, steps: int, warmup: int, gamma: float = 1.0, block: int = 2048)
                          "elementwise_max_rel_err": float((diff / np.maximum(np.abs(ref), 1e-300)).max())}
     except Exception as e:  # noqa: BLE001 -- the timing stands without the check
         out["errors"] = {"skipped": str(e)}
+    # the adjoint of the score is the probability that a path passes through each cell:
+    # exactly 1 at the first and the last cell, which every path visits
+    out["adjoint_check"] = {"first_cell": float(gC[0, 0]), "last_cell": float(gC[-1, -1]), "exact": 1.0,
+                            "min": float(gC.min())}
     return out
 
 
