@@ -64,7 +64,8 @@ def grad_err(got, want, cut=1e-3):
     return el, nw
 
 
-SHAPES = [(1, 1), (1, 37), (53, 1), (64, 64), (65, 63), (130, 257), (300, 200), (257, 1031), (300, 2500)]
+SHAPES = [(1, 1), (1, 37), (53, 1), (200, 1), (129, 3), (64, 64), (65, 63), (130, 257), (300, 200), (257, 1031),
+          (300, 2500)]
 
 
 @pytest.mark.parametrize("gamma", [0.1, 1.0])
