@@ -22,6 +22,8 @@
 #include "wf_common.h"
 #include "wf_soft.h"
 
+#include <type_traits>
+
 namespace wf {
 namespace {
 
@@ -554,8 +556,11 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
       if (pubband && 4 * (g0 + PD) > kPub &&
           !lds_wait_ge(&sh.pubd, (uint32_t)(4 * (g0 + PD) - kPub), &sh.abort, a.ctl, waited))
         return false;
-      // one 4-step group; false when a wait has to give up
-      auto group = [&](int k) -> bool {
+      // One 4-step group; false when a wait has to give up.  PATH: 0 picks the interior or
+      // the edge path per group, 1 takes the interior path, 2 the edge path (which is right
+      // for every group, only slower).
+      auto group = [&](int k, auto path) -> bool {
+        constexpr int PATH = decltype(path)::value;
         const int64_t g = g0 + k;
         if constexpr (!BOTTOM) {
           // The counter read issued a group ago, into a scalar before any of this group's
@@ -595,7 +600,7 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
         // this lane's column at step 4g (32-bit: n < 2^31, and the edge path below runs in
         // every band's first and last groups, on the critical path of the band below's start)
         const int j0 = n32 + 62 - lane - 4 * (int)g;
-        const bool interior = g >= g_lo && g < g_hi;
+        const bool interior = PATH == 1 || (PATH == 0 && g >= g_lo && g < g_hi);
         Vec4<T> out;
         if (interior) {
 #pragma unroll
@@ -664,9 +669,25 @@ __device__ __forceinline__ bool sb_compute(const T* __restrict__ Dp, T* __restri
         }
         return true;
       };
+      if constexpr (HAS_GD) {
+        // the g_D registers need constant indices: every group of the block unrolled
 #pragma unroll
-      for (int k = 0; k < PD; ++k)
-        if (!group(k)) return false;
+        for (int k = 0; k < PD; ++k)
+          if (!group(k, std::integral_constant<int, 0>())) return false;
+      } else if (g0 >= g_lo && g0 + PD <= g_hi) {
+        // Interior blocks, nearly all of them, unrolled with the interior path only; the few
+        // edge blocks at a band's two ends loop over one copy of the edge path.  Half the
+        // code of unrolling both paths: a band starts on a compute unit whose instruction
+        // cache has never held the loop, and the fetch of each new line is on the critical
+        // path of the band above.
+#pragma unroll
+        for (int k = 0; k < PD; ++k)
+          if (!group(k, std::integral_constant<int, 1>())) return false;
+      } else {
+#pragma unroll 1
+        for (int k = 0; k < PD; ++k)
+          if (!group(k, std::integral_constant<int, 2>())) return false;
+      }
       if (!BOTTOM && lane == 0) lds_signal(&sh.used, (uint32_t)(4 * (g0 + PD) < n ? 4 * (g0 + PD) : n));
     }
     lds_signal(&sh.done, (uint32_t)(s + 1));
