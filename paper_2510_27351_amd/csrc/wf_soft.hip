@@ -419,34 +419,35 @@ __device__ __forceinline__ bool sb_store(const T* P, SoftShared& sh, const SoftA
   uint64_t waited = 0;
   for (int s = 0; s < Ks; ++s) {
     if (!lds_wait_ge(&sh.done, (uint32_t)(s + 1), &sh.abort, a.ctl, waited)) return false;
-    Vec4<T> v[K::NV];
-#pragma unroll
-    for (int k = 0; k < K::NV; ++k) {
-      const SbVec<T> q(lane, k, s, n);
-      v[k] = reversed(*reinterpret_cast<const Vec4<T>*>(P + q.lds(K::PITCH)));
-    }
     // every row real and every column in [0, n): columns n - SUB(s+1) .. n + 62 - SUB s
     if (rows == kBand && K::SUB * s >= 63 && K::SUB * (s + 1) <= n) {
+      Vec4<T> v[K::NV];
+#pragma unroll
+      for (int k = 0; k < K::NV; ++k) {
+        const SbVec<T> q(lane, k, s, n);
+        v[k] = reversed(*reinterpret_cast<const Vec4<T>*>(P + q.lds(K::PITCH)));
+      }
 #pragma unroll
       for (int k = 0; k < K::NV; ++k) {
         const SbVec<T> q(lane, k, s, n);
         store4<T>(ro, (uint32_t)(q.i * ldgc + q.c_lo) * es, v[k]);
       }
     } else {
-      // unrolled like the rest: a loop over k would index v at run time and put it in
-      // scratch memory
-#pragma unroll
+      // the edge sub-chunks at a band's two ends: one vector at a time, in a loop (one copy
+      // of this code instead of sixteen)
+#pragma unroll 1
       for (int k = 0; k < K::NV; ++k) {
         const SbVec<T> q(lane, k, s, n);
         if (q.i >= rows) continue;
+        const Vec4<T> x = reversed(*reinterpret_cast<const Vec4<T>*>(P + q.lds(K::PITCH)));
         if (q.c_lo >= 0 && q.c_lo + 4 <= n) {
-          store4<T>(ro, (uint32_t)(q.i * ldgc + q.c_lo) * es, v[k]);
+          store4<T>(ro, (uint32_t)(q.i * ldgc + q.c_lo) * es, x);
           continue;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int c = q.c_lo + e;
-          if (c >= 0 && c < n) store1<T>(ro, (uint32_t)(q.i * ldgc + c) * es, v[k].v[e]);
+          if (c >= 0 && c < n) store1<T>(ro, (uint32_t)(q.i * ldgc + c) * es, x.v[e]);
         }
       }
     }
