@@ -40,6 +40,11 @@
 // The publisher has a wave of its own so that nothing delays the handoff, which sits on
 // the critical path of the whole sweep.  G (16/32/64, the "tile width") is the handoff
 // granularity.
+//
+// The same pipeline runs the soft-min variant of the recurrence (wf_soft_forward): with the
+// SOFT option the compute wave applies the soft-min cell to values in the scaled domain
+// y = D log2(e) / gamma, the publisher hands the last row on in that domain, and the storer
+// writes D = y gamma ln 2.
 #include "wf_common.h"
 #include "wf_soft.h"
 
