@@ -144,6 +144,26 @@ def test_backward_f32_with_upstream(shape, oracle_mod):
     assert el <= bar and nw <= bar
 
 
+@pytest.mark.parametrize("gamma", [0.01, 10.0])
+def test_temperature_extremes(gamma, oracle_mod):
+    """gamma = 0.01 (weights of 2^(-100 x) for a unit gap: nearly the min-plus sweep, most
+    exponentials underflow to 0) and gamma = 10 (nearly uniform weights), float64, forward
+    and adjoint with an upstream gD, across three bands."""
+    shape = (130, 257)
+    C = inputs.uniform(*shape, seed=61, dtype=torch.float64)
+    gD = inputs.uniform(*shape, seed=62, dtype=torch.float64, lo=-1.0, hi=1.0)
+    Cd = C.to(DEV)
+    D, score = wf.soft_forward(Cd, gamma)
+    Dn = oracle_mod.soft_forward(C.numpy(), gamma)
+    ferr = rel(D.cpu().numpy(), Dn)
+    g = wf.soft_backward(Cd, D, gamma, g_score=torch.tensor(0.5, dtype=torch.float64), g_D=gD.to(DEV))
+    want = oracle_mod.soft_backward(C.numpy(), Dn, gamma, gD=gD.numpy(), gscore=0.5)
+    gerr = float(np.max(np.abs(g.cpu().numpy() - want)) / max(1e-300, np.max(np.abs(want))))
+    bar = f64_grad_bar(*shape, float(np.max(np.abs(Dn))), gamma)
+    print(f"soft gamma={gamma}: forward max rel err {ferr:.2e}, adjoint {gerr:.2e} (bar {bar:.2e})")
+    assert ferr <= 1e-10 and gerr <= bar
+
+
 def test_leading_dimensions(oracle_mod):
     m, n, gamma = 150, 90, 0.3
     C = inputs.uniform(m, n, seed=41, dtype=torch.float64)
